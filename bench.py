@@ -1,0 +1,308 @@
+"""Benchmark of libbitrev on one MI355X.
+
+A step is one in-place bit-reversed permutation of 2^24 complex64 elements
+(128 MiB, real and imaginary parts N(0, 1) from seed 2), already resident in
+HBM, with the library's default plan.  Between steps a 1 GiB scratch write
+evicts the array from L2 and the 256 MiB Infinity Cache (outside the timed
+interval), so every step reads and writes HBM.  HIP events on the launch
+stream time each step.
+
+Prints one JSON line: the effective bandwidth 2 n s / t (GB/s), the roofline
+block of the tile kernel, the CPU oracle baseline, and context figures (copy
+bandwidth under the same flush policy, out of place, the tile-width sweep,
+the batched-vs-loop speedup on 4096 uneven arrays).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD specification
+FLUSH_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile_inplace_c64_2p24.txt")
+KERNEL_SOURCES = ("paper_1708_01873_amd/csrc/bitrev_device.hpp",
+                  "paper_1708_01873_amd/csrc/bitrev_kernels.inl")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """Per-call HIP-event timing on torch's current stream (the stream every
+    library call here is launched on), with a cache flush between calls."""
+
+    def __init__(self, torch, flush: bool):
+        self.torch = torch
+        self.flush = flush
+        self.scratch = torch.empty(FLUSH_BYTES // 4, dtype=torch.int32, device="cuda") if flush else None
+        self.tick = 0
+
+    def _flush(self):
+        if self.scratch is not None:
+            self.tick += 1
+            self.scratch.fill_(self.tick)
+
+    def time(self, fn, reps: int, warmup: int = 1) -> list[float]:
+        torch = self.torch
+        for _ in range(warmup):
+            self._flush()
+            fn()
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(reps):
+            self._flush()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs]  # ms
+
+
+def gbs(nbytes: float, ms: float) -> float:
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def read_traffic(bytes_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    key, _, val = line.partition(":")
+                    kv[key.strip()] = val.strip()
+        if kv.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(host, target_s: float = 10.0, max_reps: int = 20):
+    """The oracle's in-place permutation of the same array on one host core,
+    repeated until about target_s seconds have run."""
+    import numpy as np
+    import oracle
+    a = host.copy()
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.inplace(a)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or reps >= max_reps:
+            break
+    ok = np.array_equal(a.view(np.uint8), (host if reps % 2 == 0 else oracle.outofplace(host)).view(np.uint8))
+    return reps, el, ok
+
+
+def batched_speedup(torch, br, reps: int):
+    """4096 complex64 arrays, log2 n uniform in [8, 20] (seed 5): one replay
+    of the captured batched launch vs an eager loop of per-array in-place
+    calls, and that loop captured into a graph."""
+    from paper_1708_01873_amd import workloads
+    from paper_1708_01873_amd.graph import BatchedGraph
+    seed = workloads.SEEDS["c4"]
+    offsets, log2n = workloads.batched_layout(4096, 8, 20, seed)
+    total = int(offsets[-1])
+    x = workloads.device_normal(total, seed + 1000, torch.complex64)
+    off = torch.from_numpy(offsets).cuda()
+    l2 = torch.from_numpy(log2n).cuda()
+    nbytes = 2.0 * total * 8
+    g = BatchedGraph(x, off, l2)
+    views = [x[int(offsets[a]):int(offsets[a + 1])] for a in range(4096)]
+    ptrs = [(v.data_ptr(), int(log2n[a])) for a, v in enumerate(views)]
+    lib = br.lib()
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def loop():
+        for p, k in ptrs:
+            st = lib.bitrev_inplace(p, k, 8, stream)
+            if st:
+                raise br.BitrevError(st, "bitrev_inplace")
+
+    loop_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(loop_graph):
+        cap_stream = torch.cuda.current_stream().cuda_stream
+        for p, k in ptrs:
+            lib.bitrev_inplace(p, k, 8, cap_stream)
+    timer = Timer(torch, flush=True)
+    t_graph = timer.time(g.replay, reps)
+    t_loop = timer.time(loop, reps)
+    t_loopg = timer.time(loop_graph.replay, reps)
+    med = statistics.median
+    return {
+        "workload": "4096 complex64 arrays, log2n uniform [8,20], seed 5",
+        "elements": total,
+        "plan": g.plan,
+        "graph_ms": med(t_graph),
+        "graph_GBps": gbs(nbytes, med(t_graph)),
+        "eager_loop_ms": med(t_loop),
+        "eager_loop_GBps": gbs(nbytes, med(t_loop)),
+        "loop_in_graph_ms": med(t_loopg),
+        "speedup_vs_eager_loop": med(t_loop) / med(t_graph),
+        "speedup_vs_loop_in_graph": med(t_loopg) / med(t_graph),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline steps (for profiler runs)")
+    ap.add_argument("--hot", action="store_true", help="do not flush caches between steps")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; the multi-GPU form is a design "
+              "(see the sharding section of the design notes), so --gpus must be 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1708_01873_amd as br
+    from paper_1708_01873_amd import workloads
+
+    if not os.path.exists(br.LIBRARY):
+        import __graft_entry__
+        __graft_entry__.build()
+    br.lib()
+    torch.cuda.set_device(0)
+    k, s = 24, 8
+    n = 1 << k
+    nbytes = 2.0 * n * s
+    log("generating complex64 n=2^24 (seed %d)" % workloads.SEEDS["c2"])
+    host = workloads.complex64_normal(k, workloads.SEEDS["c2"])
+    x = torch.from_numpy(host).cuda()
+    plan = br.bitrev_plan_query(k, s)
+    timer = Timer(torch, flush=not args.hot)
+
+    def step():
+        br.bitrev_inplace(x, k)
+
+    log("headline: %d warmup + %d timed in-place steps, plan %s" % (args.warmup, args.steps, plan))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times = timer.time(step, args.steps, warmup=args.warmup)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mean_ms = statistics.fmean(times)
+    value = gbs(nbytes, mean_ms)
+
+    # parity of the final state: an even number of applications is the input
+    import oracle
+    applied = args.steps + args.warmup
+    got = x.cpu().numpy()
+    want = host if applied % 2 == 0 else oracle.outofplace(host)
+    bit_exact = bool(np.array_equal(got.view(np.uint8), want.view(np.uint8)))
+    log("headline %.1f GB/s (mean %.4f ms), bit_exact=%s" % (value, mean_ms, bit_exact))
+
+    traffic = read_traffic(nbytes)
+    out = {
+        "metric": "effective GB/s (2*n*elem_size/time) of the in-place bit-reversed permutation",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mean_ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic: real and imaginary parts i.i.d. N(0,1) float32, numpy PCG64 seed 2",
+        "config": {"workload": "in-place bitrev, complex64, n=2^24 (128 MiB), HBM-resident, "
+                               "caches flushed between steps" if not args.hot else
+                               "in-place bitrev, complex64, n=2^24 (128 MiB), hot caches",
+                   "log2n": k, "elem_size": s, "tile_bits": plan["tile_bits"],
+                   "grid_blocks": plan["grid_blocks"], "block_threads": plan["block_threads"]},
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "bit_exact": bit_exact,
+        "wall_s_timed_loop": round(wall, 4),
+        "step_ms_min_median_max": [round(min(times), 5), round(statistics.median(times), 5),
+                                   round(max(times), 5)],
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(value, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(value / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic, 1),
+            "kernel": "k_tile_inplace<8,%d,vec>" % plan["tile_bits"],
+            "algorithmic_bytes_per_launch": nbytes,
+        },
+    }
+
+    if not args.no_extras:
+        extras = {}
+        y = torch.empty_like(x)
+        c = timer.time(lambda: br.bitrev_copy(x, y), args.steps)
+        extras["copy_GBps"] = round(gbs(nbytes, statistics.fmean(c)), 2)
+        c2 = timer.time(lambda: y.copy_(x), args.steps)
+        extras["torch_copy_GBps"] = round(gbs(nbytes, statistics.fmean(c2)), 2)
+        best_copy = max(extras["copy_GBps"], extras["torch_copy_GBps"])
+        extras["pct_of_copy"] = round(100.0 * value / best_copy, 2)
+        o = timer.time(lambda: br.bitrev_outofplace(x, y), args.steps)
+        extras["outofplace_GBps"] = round(gbs(nbytes, statistics.fmean(o)), 2)
+        sweep = {}
+        for b in (4, 5, 6):
+            for order in (1, 2):
+                ti = timer.time(lambda: br.bitrev_inplace(x, k, tile_bits=b, order=order), args.steps)
+                to = timer.time(lambda: br.bitrev_outofplace(x, y, k, tile_bits=b, order=order),
+                                args.steps)
+                sweep["b%d_%s" % (b, "natural" if order == 1 else "balanced")] = {
+                    "inplace_GBps": round(gbs(nbytes, statistics.fmean(ti)), 2),
+                    "outofplace_GBps": round(gbs(nbytes, statistics.fmean(to)), 2)}
+        extras["tile_sweep"] = sweep
+        hot = Timer(torch, flush=False).time(step, args.steps)
+        extras["hot_cache_inplace_GBps"] = round(gbs(nbytes, statistics.fmean(hot)), 2)
+        del y
+        log("extras: %s" % json.dumps(extras))
+        try:
+            extras["batched"] = batched_speedup(torch, br, reps=5)
+            log("batched: %s" % json.dumps(extras["batched"]))
+        except torch.cuda.OutOfMemoryError as e:  # pragma: no cover
+            extras["batched"] = {"error": str(e)}
+        out["context"] = extras
+
+    if not args.no_cpu:
+        log("cpu baseline: oracle in place on the same array, one core")
+        reps, el, ok = cpu_baseline(host)
+        out["cpu_baseline"] = {
+            "value": round(gbs(nbytes * reps, el * 1e3), 4),
+            "unit": "GB/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": "the full 2^24 complex64 array, in place, %d repetitions in %.1f s" % (reps, el),
+            "bit_exact_vs_oracle_outofplace": ok,
+        }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,220 @@
+/*
+ * libbitrev -- the bit-reversed permutation of n = 2^k elements on AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operation (arXiv:1708.01873, Introduction): for an array of n = 2^k
+ * elements, the element at index i moves to index rev_k(i), where rev_k
+ * reverses exactly the low k bits of i (n = 8: 0 1 2 3 4 5 6 7 becomes
+ * 0 4 2 6 1 5 3 7).  rev_k(rev_k(i)) = i, so the permutation is its own
+ * inverse and its own adjoint, and it can be done in place by swapping each
+ * pair i < rev_k(i) once.
+ *
+ * Elements are opaque blocks of elem_size bytes (1, 2, 4, 8 or 16); their
+ * bits are moved, never interpreted, so results are byte-exact for any type
+ * (integers, floats including NaN payloads and signed zeros, complex pairs).
+ *
+ * Conventions for every entry point:
+ *   - Data pointers are DEVICE pointers (memory from hipMalloc or an
+ *     allocator built on it) on the current HIP device.  The caller owns all
+ *     memory: data, workspace and stream.  The library never allocates, frees
+ *     or synchronises on these paths, so they may be captured into a HIP graph.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued asynchronously on it, in stream order.
+ *   - Argument errors are detected on the host and returned before any HIP
+ *     call is made; nothing is enqueued then.  A failed launch returns
+ *     BITREV_ERROR_HIP and bitrev_last_hip_error() holds the hipError_t of the
+ *     calling thread.
+ *   - No C++ exception crosses this interface.  Calls are thread-safe.
+ */
+#ifndef BITREV_H
+#define BITREV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BITREV_ABI_VERSION 1
+#define BITREV_MAX_LOG2N 40
+
+typedef enum bitrev_status {
+  BITREV_SUCCESS = 0,
+  /* a null pointer, log2n outside [0, BITREV_MAX_LOG2N], elem_size not in
+   * {1,2,4,8,16}, a pointer not aligned to elem_size, a negative count, or a
+   * config field out of range */
+  BITREV_ERROR_INVALID_VALUE = 1,
+  /* source and destination ranges overlap: use the in-place entry point */
+  BITREV_ERROR_ALIAS = 2,
+  /* batched workspace missing, misaligned or smaller than
+   * bitrev_batched_workspace_size() */
+  BITREV_ERROR_WORKSPACE = 3,
+  /* a HIP runtime call or kernel launch failed; see bitrev_last_hip_error() */
+  BITREV_ERROR_HIP = 4,
+  /* valid arguments that this build cannot run: a forced tile width that is
+   * not compiled or whose LDS does not fit the device, or more than 2^32
+   * middle-bit tiles */
+  BITREV_ERROR_NOT_SUPPORTED = 5
+} bitrev_status_t;
+
+/* Optional launch configuration for the *_ex entry points.  A zero field
+ * means "library choice" (tuning table, else built-in default). */
+typedef struct bitrev_config {
+  int tile_bits;   /* b: tiles of 2^b x 2^b elements, 0..7 (0 = choose); the
+                    * method splits the index bits as [high b | middle | low b] */
+  int grid_blocks; /* workgroups launched; >0 makes the kernel loop over its
+                    * work items with a grid stride (persistent); 0 = choose */
+  int order;       /* work-item order: 0 = choose, 1 = natural, 2 = balanced
+                    * bit dealing (spreads tile rows over HBM channels) */
+  int reserved;    /* must be 0 */
+} bitrev_config_t;
+
+/* Which code path and geometry a call uses (bitrev_plan_query). */
+typedef enum bitrev_path {
+  BITREV_PATH_NONE = 0,  /* nothing to do (in place with n <= 2, or no rows) */
+  BITREV_PATH_WAVE = 1,  /* n <= 64: one wavefront per array, lane shuffles */
+  BITREV_PATH_TILE = 2,  /* tiles of 2^b x 2^b staged through LDS */
+  BITREV_PATH_BATCHED = 3 /* persistent batched kernel (tiles + whole-array LDS) */
+} bitrev_path_t;
+
+typedef struct bitrev_plan {
+  int path;             /* bitrev_path_t */
+  int tile_bits;        /* b */
+  int mid_bits;         /* m = log2n - 2b */
+  int block_threads;    /* threads per workgroup */
+  int grid_blocks;      /* workgroups launched */
+  int order;            /* 1 natural, 2 balanced */
+  int vector_access;    /* 1: 16-byte global accesses; 0: one element per access */
+  int reserved;
+  uint64_t work_items;  /* tile pairs (in place) or tiles (out of place), all rows */
+  uint64_t lds_bytes;   /* LDS per workgroup */
+} bitrev_plan_t;
+
+/* ------------------------------------------------------------------------ */
+/* Plain permutations                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* In place: data[0 .. 2^log2n) is replaced by its bit-reversed permutation
+ * (Introduction: swap i and rev(i) once per pair).  data is a device
+ * pointer to 2^log2n contiguous elements of elem_size bytes, aligned to
+ * elem_size. */
+bitrev_status_t bitrev_inplace(void* data, int log2n, size_t elem_size, void* stream);
+
+/* Out of place: dst[rev(i)] = src[i] for every i < 2^log2n (Introduction,
+ * the buffered method's out-of-place statement).  src and dst are device
+ * pointers to non-overlapping arrays of 2^log2n elements; overlapping ranges
+ * return BITREV_ERROR_ALIAS. */
+bitrev_status_t bitrev_outofplace(const void* src, void* dst, int log2n, size_t elem_size,
+                                  void* stream);
+
+/* `rows` independent arrays of 2^log2n elements stored back to back
+ * (row-major [rows][2^log2n]); each row is permuted on its own.
+ * src == dst means in place; otherwise the two ranges must not overlap.
+ * rows == 0 is a no-op.  This is the forward and the backward of the
+ * differentiable form: the permutation's adjoint is itself. */
+bitrev_status_t bitrev_rows(const void* src, void* dst, int log2n, int64_t rows,
+                            size_t elem_size, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched: many arrays of different lengths in one persistent launch        */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace bitrev_batched needs for num_arrays arrays
+ * ((num_arrays + 3) * 8, rounded up to 256).  Returns 0 for num_arrays < 0. */
+size_t bitrev_batched_workspace_size(int64_t num_arrays);
+
+/* In place, every array a in [0, num_arrays): the elements
+ * data[offsets[a] .. offsets[a+1]) (counted in elements of elem_size bytes)
+ * are replaced by their bit-reversed permutation of length 2^log2n[a].
+ *   data       device pointer, data_elems elements, aligned to elem_size
+ *   offsets    device pointer, num_arrays + 1 int64 (CSR style)
+ *   log2n      device pointer, num_arrays int32
+ *   workspace  device pointer, >= bitrev_batched_workspace_size(num_arrays)
+ *              bytes, 8-byte aligned; owned by the caller, overwritten, and
+ *              holds after the call: [0] the number of arrays rejected,
+ *              [1] the first rejected array (or -1) -- see
+ *              bitrev_batched_errors()
+ * Two kernels are enqueued: a one-workgroup prep kernel that checks every
+ * array (offsets[a+1] - offsets[a] == 2^log2n[a], 0 <= offsets[a],
+ * offsets[a+1] <= data_elems, 0 <= log2n[a] <= BITREV_MAX_LOG2N) and scans
+ * the per-array work counts into the workspace, then the persistent kernel.
+ * A rejected array is left untouched; the others are still permuted.
+ * Arrays must not overlap (the length check makes valid ones disjoint). */
+bitrev_status_t bitrev_batched(void* data, int64_t data_elems, const int64_t* offsets,
+                               const int32_t* log2n, int64_t num_arrays, size_t elem_size,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Synchronous debug helper: waits for `stream`, then reads the rejection
+ * count and first rejected array that the last bitrev_batched on this
+ * workspace wrote.  Either output pointer may be NULL. */
+bitrev_status_t bitrev_batched_errors(const void* workspace, int64_t* num_rejected,
+                                      int64_t* first_rejected, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Explicit configuration (autotuner, tile-width sweeps)                     */
+/* ------------------------------------------------------------------------ */
+
+/* As the plain calls, with a launch configuration (NULL = library choice).
+ * A tile width that is not compiled for elem_size, or whose LDS does not fit
+ * the device, returns BITREV_ERROR_NOT_SUPPORTED. */
+bitrev_status_t bitrev_inplace_ex(void* data, int log2n, size_t elem_size,
+                                  const bitrev_config_t* cfg, void* stream);
+bitrev_status_t bitrev_outofplace_ex(const void* src, void* dst, int log2n, size_t elem_size,
+                                     const bitrev_config_t* cfg, void* stream);
+bitrev_status_t bitrev_rows_ex(const void* src, void* dst, int log2n, int64_t rows,
+                               size_t elem_size, const bitrev_config_t* cfg, void* stream);
+bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t* offsets,
+                                  const int32_t* log2n, int64_t num_arrays, size_t elem_size,
+                                  void* workspace, size_t workspace_bytes,
+                                  const bitrev_config_t* cfg, void* stream);
+
+/* The plan a call would use, without launching anything.  mode: 0 in place,
+ * 1 out of place, 2 batched (log2n ignored).  Uses the current device's
+ * properties when a device is present, else MI355X figures (256 compute
+ * units, 160 KiB LDS). */
+bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int mode,
+                                  const bitrev_config_t* cfg, bitrev_plan_t* plan);
+
+/* Load a tuning table (text; see bitrev_tuning_format()).  NULL restores the
+ * built-in defaults.  A file that cannot be read or has a malformed line is
+ * rejected with BITREV_ERROR_INVALID_VALUE and the table in use is kept.  If
+ * the environment variable BITREV_TUNING_FILE names a file, it is loaded at
+ * the first call that needs a plan. */
+bitrev_status_t bitrev_load_tuning(const char* path);
+
+/* One line describing the tuning file's format. */
+const char* bitrev_tuning_format(void);
+
+/* ------------------------------------------------------------------------ */
+/* Reference copy (the HBM roofline denominator), status, version            */
+/* ------------------------------------------------------------------------ */
+
+/* dst[0 .. bytes) = src[0 .. bytes): a plain streaming copy with the same
+ * byte count as an out-of-place permutation, used to measure attainable HBM
+ * bandwidth.  Ranges must not overlap. */
+bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+const char* bitrev_status_string(bitrev_status_t status);
+int bitrev_last_hip_error(void);
+int bitrev_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Host mirrors of the kernels' index arithmetic (the same source, compiled */
+/* for the host), so that tests can check it on a machine without a GPU.     */
+/* ------------------------------------------------------------------------ */
+
+/* rev_j(v): the low j bits of v reversed, 0 <= j <= 32. */
+uint32_t bitrev_debug_rev(uint32_t v, int j);
+/* Number of tile pairs {y, rev_m(y)} with y <= rev_m(y), 0 <= m <= 32. */
+uint64_t bitrev_debug_pair_count(int m);
+/* The w-th such y in the kernels' enumeration order (balanced: 0 or 1). */
+uint32_t bitrev_debug_pair_at(int m, uint64_t w, int balanced);
+/* The balanced bit dealing of a width-bit value. */
+uint32_t bitrev_debug_spread(uint32_t w, int width);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BITREV_H */

@@ -1,0 +1,313 @@
+"""libbitrev: the bit-reversed permutation of n = 2^k elements on MI355X.
+
+A thin ctypes binding over the C ABI in ``include/bitrev.h`` (the shared
+library ``libbitrev.so`` built from ``csrc/`` by ``build.py``).  The functions
+here have the C entry points' names and only marshal arguments: tensors give
+their device pointer and element size, the stream defaults to torch's current
+stream.  Every step of the permutation runs in the HIP kernels; if the library
+is not built, every call raises.
+
+The operation (arXiv:1708.01873, Introduction): element i of an array of
+2^k elements moves to index rev_k(i), the low k bits of i reversed.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(PKG_DIR, "libbitrev.so")
+
+SUCCESS = 0
+ERROR_INVALID_VALUE = 1
+ERROR_ALIAS = 2
+ERROR_WORKSPACE = 3
+ERROR_HIP = 4
+ERROR_NOT_SUPPORTED = 5
+
+PATH_NONE, PATH_WAVE, PATH_TILE, PATH_BATCHED = 0, 1, 2, 3
+MODE_INPLACE, MODE_OUTOFPLACE, MODE_BATCHED = 0, 1, 2
+ORDER_DEFAULT, ORDER_NATURAL, ORDER_BALANCED = 0, 1, 2
+
+
+class BitrevError(RuntimeError):
+    """A libbitrev call returned a status other than BITREV_SUCCESS."""
+
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = "%s: %s" % (where, status_string(status))
+        if status == ERROR_HIP:
+            msg += " (hipError %d)" % _load().bitrev_last_hip_error()
+        super().__init__(msg)
+
+
+class Config(ctypes.Structure):
+    """bitrev_config_t: zero fields mean "library choice"."""
+    _fields_ = [("tile_bits", ctypes.c_int), ("grid_blocks", ctypes.c_int),
+                ("order", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+class Plan(ctypes.Structure):
+    """bitrev_plan_t."""
+    _fields_ = [("path", ctypes.c_int), ("tile_bits", ctypes.c_int), ("mid_bits", ctypes.c_int),
+                ("block_threads", ctypes.c_int), ("grid_blocks", ctypes.c_int),
+                ("order", ctypes.c_int), ("vector_access", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("work_items", ctypes.c_uint64),
+                ("lds_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+_VP, _I, _I64, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+_CFGP = ctypes.POINTER(Config)
+_SIGNATURES = {
+    "bitrev_inplace": ([_VP, _I, _SZ, _VP], _I),
+    "bitrev_outofplace": ([_VP, _VP, _I, _SZ, _VP], _I),
+    "bitrev_rows": ([_VP, _VP, _I, _I64, _SZ, _VP], _I),
+    "bitrev_batched_workspace_size": ([_I64], _SZ),
+    "bitrev_batched": ([_VP, _I64, _VP, _VP, _I64, _SZ, _VP, _SZ, _VP], _I),
+    "bitrev_batched_errors": ([_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _VP], _I),
+    "bitrev_inplace_ex": ([_VP, _I, _SZ, _CFGP, _VP], _I),
+    "bitrev_outofplace_ex": ([_VP, _VP, _I, _SZ, _CFGP, _VP], _I),
+    "bitrev_rows_ex": ([_VP, _VP, _I, _I64, _SZ, _CFGP, _VP], _I),
+    "bitrev_batched_ex": ([_VP, _I64, _VP, _VP, _I64, _SZ, _VP, _SZ, _CFGP, _VP], _I),
+    "bitrev_plan_query": ([_I, _SZ, _I64, _I, _CFGP, ctypes.POINTER(Plan)], _I),
+    "bitrev_load_tuning": ([ctypes.c_char_p], _I),
+    "bitrev_tuning_format": ([], ctypes.c_char_p),
+    "bitrev_copy": ([_VP, _VP, _SZ, _VP], _I),
+    "bitrev_status_string": ([_I], ctypes.c_char_p),
+    "bitrev_last_hip_error": ([], _I),
+    "bitrev_abi_version": ([], _I),
+    "bitrev_debug_rev": ([ctypes.c_uint32, _I], ctypes.c_uint32),
+    "bitrev_debug_pair_count": ([_I], ctypes.c_uint64),
+    "bitrev_debug_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
+    "bitrev_debug_spread": ([ctypes.c_uint32, _I], ctypes.c_uint32),
+}
+EXPORTED = tuple(_SIGNATURES)
+
+
+def _load() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBRARY):
+            raise RuntimeError(
+                "libbitrev.so is not built (%s); run `python -m paper_1708_01873_amd.build` "
+                "or __graft_entry__.build()" % LIBRARY)
+        lib = ctypes.CDLL(LIBRARY)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded C library (raises if it is not built)."""
+    return _load()
+
+
+def status_string(status: int) -> str:
+    return _load().bitrev_status_string(int(status)).decode()
+
+
+def abi_version() -> int:
+    return _load().bitrev_abi_version()
+
+
+def _check(status: int, where: str) -> None:
+    if status != SUCCESS:
+        raise BitrevError(status, where)
+
+
+def _config(tile_bits=0, grid_blocks=0, order=0, config=None):
+    if config is not None:
+        return config
+    if tile_bits or grid_blocks or order:
+        return Config(int(tile_bits), int(grid_blocks), int(order), 0)
+    return None
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _tensor_args(t, what: str):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % what)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor (libbitrev runs on the GPU only)" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return t.data_ptr(), t.element_size()
+
+
+def _log2_exact(n: int) -> int:
+    k = int(n).bit_length() - 1
+    if n <= 0 or (1 << k) != n:
+        raise ValueError("length %d is not a power of two" % n)
+    return k
+
+
+def bitrev_inplace(data, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0, order=0,
+                   config=None, stream=None):
+    """Replace ``data`` (2^log2n contiguous elements) by its bit-reversed
+    permutation.  ``log2n`` defaults to log2(data.numel())."""
+    ptr, s = _tensor_args(data, "data")
+    k = _log2_exact(data.numel()) if log2n is None else int(log2n)
+    cfg = _config(tile_bits, grid_blocks, order, config)
+    L = _load()
+    if cfg is None:
+        _check(L.bitrev_inplace(ptr, k, s, _stream(stream)), "bitrev_inplace")
+    else:
+        _check(L.bitrev_inplace_ex(ptr, k, s, ctypes.byref(cfg), _stream(stream)),
+               "bitrev_inplace_ex")
+    return data
+
+
+def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0,
+                      order=0, config=None, stream=None):
+    """dst[rev(i)] = src[i]; allocates ``dst`` like ``src`` when not given."""
+    if dst is None:
+        import torch
+        dst = torch.empty_like(src)
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2 or src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same element size and length")
+    k = _log2_exact(src.numel()) if log2n is None else int(log2n)
+    cfg = _config(tile_bits, grid_blocks, order, config)
+    L = _load()
+    if cfg is None:
+        _check(L.bitrev_outofplace(sp, dp, k, s, _stream(stream)), "bitrev_outofplace")
+    else:
+        _check(L.bitrev_outofplace_ex(sp, dp, k, s, ctypes.byref(cfg), _stream(stream)),
+               "bitrev_outofplace_ex")
+    return dst
+
+
+def bitrev_rows(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0,
+                order=0, config=None, stream=None):
+    """Permute every row of 2^log2n elements (default: the last dimension);
+    ``dst is src`` works in place.  Allocates ``dst`` when not given."""
+    if dst is None:
+        import torch
+        dst = torch.empty_like(src)
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2 or src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same element size and length")
+    if log2n is None:
+        if src.dim() == 0:
+            raise ValueError("bitrev_rows needs at least one dimension")
+        k = _log2_exact(src.shape[-1])
+    else:
+        k = int(log2n)
+    n = 1 << k
+    if src.numel() % n:
+        raise ValueError("%d elements are not a whole number of rows of %d" % (src.numel(), n))
+    rows = src.numel() // n
+    cfg = _config(tile_bits, grid_blocks, order, config)
+    L = _load()
+    if cfg is None:
+        _check(L.bitrev_rows(sp, dp, k, rows, s, _stream(stream)), "bitrev_rows")
+    else:
+        _check(L.bitrev_rows_ex(sp, dp, k, rows, s, ctypes.byref(cfg), _stream(stream)),
+               "bitrev_rows_ex")
+    return dst
+
+
+def bitrev_batched_workspace_size(num_arrays: int) -> int:
+    return int(_load().bitrev_batched_workspace_size(int(num_arrays)))
+
+
+def bitrev_batched(data, offsets, log2n, workspace=None, *, tile_bits=0, grid_blocks=0, order=0,
+                   config=None, stream=None):
+    """In place on every packed array [offsets[a], offsets[a+1]) of ``data``
+    (lengths 2^log2n[a]).  ``offsets`` (int64, num+1) and ``log2n`` (int32,
+    num) are device tensors; ``workspace`` is a device byte tensor of at least
+    bitrev_batched_workspace_size(num) bytes (allocated when not given, which
+    is not allowed under graph capture)."""
+    import torch
+    dp, s = _tensor_args(data, "data")
+    if offsets.dtype != torch.int64 or log2n.dtype != torch.int32:
+        raise TypeError("offsets must be int64 and log2n int32")
+    op, _ = _tensor_args(offsets, "offsets")
+    lp, _ = _tensor_args(log2n, "log2n")
+    num = log2n.numel()
+    if offsets.numel() != num + 1:
+        raise ValueError("offsets must have num_arrays + 1 entries")
+    need = bitrev_batched_workspace_size(num)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=data.device)
+    wp, _ = _tensor_args(workspace, "workspace")
+    wbytes = workspace.numel() * workspace.element_size()
+    cfg = _config(tile_bits, grid_blocks, order, config)
+    L = _load()
+    if cfg is None:
+        _check(L.bitrev_batched(dp, data.numel(), op, lp, num, s, wp, wbytes, _stream(stream)),
+               "bitrev_batched")
+    else:
+        _check(L.bitrev_batched_ex(dp, data.numel(), op, lp, num, s, wp, wbytes,
+                                   ctypes.byref(cfg), _stream(stream)), "bitrev_batched_ex")
+    return data
+
+
+def bitrev_batched_errors(workspace, stream=None) -> tuple[int, int]:
+    """(arrays rejected, first rejected or -1) of the last batched call on
+    ``workspace``; waits for the stream."""
+    wp, _ = _tensor_args(workspace, "workspace")
+    nrej, first = ctypes.c_int64(0), ctypes.c_int64(-1)
+    _check(_load().bitrev_batched_errors(wp, ctypes.byref(nrej), ctypes.byref(first),
+                                         _stream(stream)), "bitrev_batched_errors")
+    return nrej.value, first.value
+
+
+def bitrev_copy(src, dst, stream=None):
+    """The reference streaming copy (same bytes as an out-of-place pass)."""
+    sp, _ = _tensor_args(src, "src")
+    dp, _ = _tensor_args(dst, "dst")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    _check(_load().bitrev_copy(sp, dp, nbytes, _stream(stream)), "bitrev_copy")
+    return dst
+
+
+def bitrev_plan_query(log2n: int, elem_size: int, rows: int = 1, mode: int = MODE_INPLACE,
+                      *, tile_bits=0, grid_blocks=0, order=0, config=None) -> dict:
+    """The plan a call would use (no launch)."""
+    cfg = _config(tile_bits, grid_blocks, order, config)
+    p = Plan()
+    _check(_load().bitrev_plan_query(int(log2n), int(elem_size), int(rows), int(mode),
+                                     ctypes.byref(cfg) if cfg is not None else None,
+                                     ctypes.byref(p)), "bitrev_plan_query")
+    return p.as_dict()
+
+
+def bitrev_load_tuning(path: Optional[str]) -> None:
+    """Load a tuning table file (None restores the built-in defaults)."""
+    _check(_load().bitrev_load_tuning(None if path is None else os.fsencode(path)),
+           "bitrev_load_tuning")
+
+
+def bitrev_tuning_format() -> str:
+    return _load().bitrev_tuning_format().decode()
+
+
+__all__ = [
+    "BitrevError", "Config", "Plan", "lib", "abi_version", "status_string",
+    "bitrev_inplace", "bitrev_outofplace", "bitrev_rows", "bitrev_batched",
+    "bitrev_batched_workspace_size", "bitrev_batched_errors", "bitrev_copy",
+    "bitrev_plan_query", "bitrev_load_tuning", "bitrev_tuning_format",
+]

@@ -1,0 +1,573 @@
+// The C ABI of libbitrev: argument validation (before any HIP call), the
+// plan (which path, tile width, grid), the tuning table, and the launches.
+#include <errno.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "bitrev.h"
+#include "bitrev_device.hpp"
+#include "bitrev_launch.hpp"
+
+namespace {
+
+using namespace bitrev;
+
+thread_local int g_last_hip_error = 0;
+
+bitrev_status_t hip_fail(hipError_t e) {
+  g_last_hip_error = (int)e;
+  return BITREV_ERROR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Device properties (cached per device).
+// ---------------------------------------------------------------------------
+struct DeviceInfo {
+  int cus = 256;                 // compute units
+  size_t lds_per_block = 163840; // LDS bytes a workgroup may use
+  int xcds = 8;                  // XCDs the dispatcher deals workgroups over
+};
+
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mu;
+bool g_dev_known[kMaxDevices];
+DeviceInfo g_dev[kMaxDevices];
+
+// The current device's properties; MI355X figures when `allow_default` and
+// no device is present (plan queries on a host without a GPU).
+bitrev_status_t device_info(DeviceInfo* out, bool allow_default) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    if (allow_default) {
+      (void)hipGetLastError();
+      *out = DeviceInfo();
+      return BITREV_SUCCESS;
+    }
+    return hip_fail(e != hipSuccess ? e : hipErrorInvalidDevice);
+  }
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  if (!g_dev_known[dev]) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    DeviceInfo d;
+    d.cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 1;
+    d.lds_per_block = p.sharedMemPerBlock;
+    // gfx950 has 32 compute units per XCD; a partitioned device shows fewer.
+    int x = (d.cus + 16) / 32;
+    if (strncmp(p.gcnArchName, "gfx942", 6) == 0) x = (d.cus + 19) / 38;
+    if (x < 1) x = 1;
+    if (const char* env = getenv("BITREV_XCDS")) {
+      const int v = atoi(env);
+      if (v >= 1 && v <= 64) x = v;
+    }
+    d.xcds = x;
+    g_dev[dev] = d;
+    g_dev_known[dev] = true;
+  }
+  *out = g_dev[dev];
+  return BITREV_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning table: (mode, elem_size, log2n or -1) -> tile bits, workgroups per
+// CU, order.  Loaded from a text file; the built-in defaults apply otherwise.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  int tile_bits = 0;
+  int wg_per_cu = 0;
+  int order = 0;
+};
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, TuneEntry> g_tune;
+std::once_flag g_tune_env_once;
+
+const char kTuningFormat[] =
+    "libbitrev tuning v1: one entry per line, '#' starts a comment; fields: mode "
+    "(inplace|outofplace|batched) elem_size log2n(-1 = any) tile_bits wg_per_cu(0 = default) "
+    "order(0 = default, 1 natural, 2 balanced)";
+
+int mode_from_name(const char* s) {
+  if (strcmp(s, "inplace") == 0) return 0;
+  if (strcmp(s, "outofplace") == 0) return 1;
+  if (strcmp(s, "batched") == 0) return 2;
+  return -1;
+}
+
+bool valid_elem_size(size_t s) { return s == 1 || s == 2 || s == 4 || s == 8 || s == 16; }
+
+bitrev_status_t load_tuning_file(const char* path) {
+  if (path == NULL) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    return BITREV_SUCCESS;
+  }
+  FILE* f = fopen(path, "r");
+  if (!f) return BITREV_ERROR_INVALID_VALUE;
+  std::map<std::tuple<int, int, int>, TuneEntry> table;
+  char line[512];
+  bool ok = true;
+  while (fgets(line, sizeof line, f)) {
+    char* hash = strchr(line, '#');
+    if (hash) *hash = '\0';
+    char mode[32];
+    int s, k, b, wg, order;
+    char extra[8];
+    const int got = sscanf(line, "%31s %d %d %d %d %d %7s", mode, &s, &k, &b, &wg, &order, extra);
+    if (got <= 0) continue;  // blank or comment-only line
+    const int md = got >= 6 ? mode_from_name(mode) : -1;
+    if (got != 6 || md < 0 || !valid_elem_size((size_t)s) || k < -1 || k > BITREV_MAX_LOG2N ||
+        b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 || order > 2) {
+      ok = false;
+      break;
+    }
+    TuneEntry t;
+    t.tile_bits = b;
+    t.wg_per_cu = wg;
+    t.order = order;
+    table[std::make_tuple(md, s, k)] = t;
+  }
+  fclose(f);
+  if (!ok) return BITREV_ERROR_INVALID_VALUE;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.swap(table);
+  return BITREV_SUCCESS;
+}
+
+void load_env_tuning() {
+  std::call_once(g_tune_env_once, [] {
+    const char* p = getenv("BITREV_TUNING_FILE");
+    if (p && *p) (void)load_tuning_file(p);
+  });
+}
+
+TuneEntry tune_lookup(int mode, int s, int k) {
+  load_env_tuning();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(mode, s, k));
+  if (it == g_tune.end()) it = g_tune.find(std::make_tuple(mode, s, -1));
+  return it == g_tune.end() ? TuneEntry() : it->second;
+}
+
+// ---------------------------------------------------------------------------
+// Plans.
+// ---------------------------------------------------------------------------
+enum { kModeInplace = 0, kModeOutofplace = 1, kModeBatched = 2 };
+
+// Built-in tile width per element size: rows of 2^b * s >= 256 bytes keep
+// every HBM access a run of whole 128-byte lines.
+int default_tile_bits(int s) {
+  switch (s) {
+    case 1: return 7;
+    case 2: return 7;
+    case 4: return 6;
+    case 8: return 5;
+    default: return 4;
+  }
+}
+
+int default_order() { return 2; }
+
+int threads_of(int s, int b, bool vec) {
+  switch (s) {
+    case 1: return tile_threads_s1(b, vec);
+    case 2: return tile_threads_s2(b, vec);
+    case 4: return tile_threads_s4(b, vec);
+    case 8: return tile_threads_s8(b, vec);
+    default: return tile_threads_s16(b, vec);
+  }
+}
+
+bool valid_config(const bitrev_config_t* c) {
+  if (!c) return true;
+  return c->tile_bits >= 0 && c->tile_bits <= kMaxTileBits && c->grid_blocks >= 0 &&
+         c->order >= 0 && c->order <= 2 && c->reserved == 0;
+}
+
+uint32_t round_up(uint64_t v, uint32_t to) {
+  const uint64_t r = (v + to - 1) / to * to;
+  return (uint32_t)(r > 0xFFFFFFFFull ? 0xFFFFFFFFull / to * to : r);
+}
+
+// Grid for `items` work items: one workgroup per item up to 2^20
+// workgroups (then a grid-stride loop), a multiple of the XCD count.
+uint32_t default_grid(uint64_t items, const DeviceInfo& d) {
+  const uint64_t cap = 1ull << 20;
+  return round_up(items < cap ? items : cap, (uint32_t)d.xcds);
+}
+
+struct Plan {
+  int path = BITREV_PATH_NONE;
+  int b = 0;
+  int m = 0;
+  int threads = 0;
+  uint32_t grid = 0;
+  int order = 2;
+  bool vec = true;
+  uint64_t items_per_seg = 0;
+  uint64_t total = 0;
+  size_t lds = 0;
+};
+
+// Plan for a plain call (mode 0 or 1) on `rows` arrays of 2^k elements.
+// align: the largest power of two (<= 16) dividing both data pointers.
+bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_config_t* cfg,
+                           size_t align, const DeviceInfo& d, Plan* p) {
+  *p = Plan();
+  if (rows == 0 || (mode == kModeInplace && k <= 1)) return BITREV_SUCCESS;
+  const int forced_b = cfg ? cfg->tile_bits : 0;
+  const TuneEntry te = tune_lookup(mode, s, k);
+  p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : default_order());
+  if (forced_b == 0 && k <= 6) {
+    p->path = BITREV_PATH_WAVE;
+    p->threads = 256;
+    const uint64_t wg = ((uint64_t)rows + 3) / 4;
+    p->grid = (uint32_t)(wg < 65536 ? wg : 65536);
+    if (cfg && cfg->grid_blocks > 0) p->grid = (uint32_t)cfg->grid_blocks;
+    p->total = (uint64_t)rows;
+    return BITREV_SUCCESS;
+  }
+  const int inplace_tiles = (mode == kModeInplace) ? 2 : 1;
+  int b;
+  if (forced_b > 0) {
+    b = forced_b;
+    if (2 * b > k || b > max_tile_bits(s) ||
+        tile_lds_bytes_for(s, b, inplace_tiles) > d.lds_per_block)
+      return BITREV_ERROR_NOT_SUPPORTED;
+  } else {
+    b = te.tile_bits ? te.tile_bits : default_tile_bits(s);
+    if (b > max_tile_bits(s)) b = max_tile_bits(s);
+    if (2 * b > k) b = k / 2;
+    while (b > 0 && tile_lds_bytes_for(s, b, inplace_tiles) > d.lds_per_block) --b;
+  }
+  const int m = k - 2 * b;
+  if (m > 32) return BITREV_ERROR_NOT_SUPPORTED;
+  const size_t vb = ((size_t)s << b) < 16 ? ((size_t)s << b) : 16;
+  p->vec = (align % vb) == 0;
+  p->path = BITREV_PATH_TILE;
+  p->b = b;
+  p->m = m;
+  p->items_per_seg = (mode == kModeInplace) ? pair_count(m) : (1ull << m);
+  if ((uint64_t)rows > (1ull << 62) / p->items_per_seg) return BITREV_ERROR_NOT_SUPPORTED;
+  p->total = p->items_per_seg * (uint64_t)rows;
+  p->threads = threads_of(s, b, p->vec);
+  p->lds = tile_lds_bytes_for(s, b, inplace_tiles);
+  if (cfg && cfg->grid_blocks > 0) {
+    p->grid = round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds);
+  } else if (te.wg_per_cu > 0) {
+    p->grid = round_up((uint64_t)te.wg_per_cu * d.cus, (uint32_t)d.xcds);
+  } else {
+    p->grid = default_grid(p->total, d);
+  }
+  return BITREV_SUCCESS;
+}
+
+// Workgroups of the batched kernel that fit on one CU at once: limited by
+// LDS (160 KiB per CU) and by 32 wavefronts per CU.
+int resident_per_cu(int threads, size_t lds) {
+  const int by_waves = 32 / ((threads + 63) / 64);
+  const int by_lds = lds ? (int)(163840 / lds) : by_waves;
+  const int r = by_waves < by_lds ? by_waves : by_lds;
+  return r < 1 ? 1 : r;
+}
+
+bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo& d, Plan* p) {
+  *p = Plan();
+  const TuneEntry te = tune_lookup(kModeBatched, s, -1);
+  int b = (cfg && cfg->tile_bits) ? cfg->tile_bits : (te.tile_bits ? te.tile_bits : default_tile_bits(s));
+  if (!(cfg && cfg->tile_bits) && b > max_tile_bits(s)) b = max_tile_bits(s);
+  if (b < kMinBatchedTileBits || b > max_tile_bits(s) ||
+      tile_lds_bytes_for(s, b, 2) > d.lds_per_block)
+    return BITREV_ERROR_NOT_SUPPORTED;
+  p->path = BITREV_PATH_BATCHED;
+  p->b = b;
+  p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : default_order());
+  p->threads = threads_of(s, b, true);
+  p->lds = tile_lds_bytes_for(s, b, 2);
+  int per_cu = te.wg_per_cu > 0 ? te.wg_per_cu : resident_per_cu(p->threads, p->lds);
+  if (cfg && cfg->grid_blocks > 0) {
+    p->grid = round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds);
+  } else {
+    p->grid = round_up((uint64_t)per_cu * d.cus, (uint32_t)d.xcds);
+  }
+  return BITREV_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// Launches.
+// ---------------------------------------------------------------------------
+hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void* dst, uint64_t n,
+                       const DeviceInfo& d, hipStream_t st) {
+  TileLaunch a;
+  a.src = src;
+  a.dst = dst;
+  a.m = p.m;
+  a.items_per_seg = p.items_per_seg;
+  a.total_items = p.total;
+  a.seg_elems = n;
+  a.balanced = p.order == 2 ? 1 : 0;
+  a.xcds = d.xcds;
+  a.grid = p.grid;
+  switch (s) {
+    case 1: return inplace ? launch_tile_inplace_s1(p.b, p.vec, a, st) : launch_tile_outofplace_s1(p.b, p.vec, a, st);
+    case 2: return inplace ? launch_tile_inplace_s2(p.b, p.vec, a, st) : launch_tile_outofplace_s2(p.b, p.vec, a, st);
+    case 4: return inplace ? launch_tile_inplace_s4(p.b, p.vec, a, st) : launch_tile_outofplace_s4(p.b, p.vec, a, st);
+    case 8: return inplace ? launch_tile_inplace_s8(p.b, p.vec, a, st) : launch_tile_outofplace_s8(p.b, p.vec, a, st);
+    default: return inplace ? launch_tile_inplace_s16(p.b, p.vec, a, st) : launch_tile_outofplace_s16(p.b, p.vec, a, st);
+  }
+}
+
+hipError_t launch_wave(int s, const Plan& p, const void* src, void* dst, int k, int64_t rows,
+                       hipStream_t st) {
+  WaveLaunch a;
+  a.src = src;
+  a.dst = dst;
+  a.k = k;
+  a.nseg = (uint64_t)rows;
+  a.grid = p.grid;
+  switch (s) {
+    case 1: return launch_wave_s1(a, st);
+    case 2: return launch_wave_s2(a, st);
+    case 4: return launch_wave_s4(a, st);
+    case 8: return launch_wave_s8(a, st);
+    default: return launch_wave_s16(a, st);
+  }
+}
+
+size_t pointer_align(const void* a, const void* b) {
+  const uintptr_t v = reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b);
+  size_t al = 16;
+  while (al > 1 && (v & (al - 1))) al >>= 1;
+  return al;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+// Common body of bitrev_inplace/outofplace/rows (+ _ex).
+bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_t s,
+                          const bitrev_config_t* cfg, void* stream, bool rows_call) {
+  // ---- validation: no HIP call before this block completes ----
+  if (src == NULL || dst == NULL) return BITREV_ERROR_INVALID_VALUE;
+  if (k < 0 || k > BITREV_MAX_LOG2N || !valid_elem_size(s) || rows < 0 || !valid_config(cfg))
+    return BITREV_ERROR_INVALID_VALUE;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % s)
+    return BITREV_ERROR_INVALID_VALUE;
+  const uint64_t n = 1ull << k;
+  if (rows > 0 && (uint64_t)rows > (1ull << 62) / (n * s)) return BITREV_ERROR_INVALID_VALUE;
+  const size_t bytes = (size_t)(n * s * (uint64_t)rows);
+  const bool inplace = (src == dst);
+  if (!inplace && overlap(src, dst, bytes)) return BITREV_ERROR_ALIAS;
+  (void)rows_call;
+  if (rows == 0 || (inplace && k <= 1)) return BITREV_SUCCESS;
+  // ---- plan and launch ----
+  DeviceInfo d;
+  bitrev_status_t st = device_info(&d, false);
+  if (st != BITREV_SUCCESS) return st;
+  Plan p;
+  st = plan_plain(inplace ? kModeInplace : kModeOutofplace, k, (int)s, rows, cfg,
+                  pointer_align(src, dst), d, &p);
+  if (st != BITREV_SUCCESS) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (p.path == BITREV_PATH_WAVE) {
+    e = launch_wave((int)s, p, src, dst, k, rows, hs);
+  } else if (p.path == BITREV_PATH_TILE) {
+    e = launch_tile(inplace, (int)s, p, src, dst, n, d, hs);
+  }
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+bitrev_status_t bitrev_inplace(void* data, int log2n, size_t elem_size, void* stream) {
+  return run_plain(data, data, log2n, 1, elem_size, NULL, stream, false);
+}
+
+bitrev_status_t bitrev_inplace_ex(void* data, int log2n, size_t elem_size,
+                                  const bitrev_config_t* cfg, void* stream) {
+  return run_plain(data, data, log2n, 1, elem_size, cfg, stream, false);
+}
+
+bitrev_status_t bitrev_outofplace(const void* src, void* dst, int log2n, size_t elem_size,
+                                  void* stream) {
+  if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;
+  return run_plain(src, dst, log2n, 1, elem_size, NULL, stream, false);
+}
+
+bitrev_status_t bitrev_outofplace_ex(const void* src, void* dst, int log2n, size_t elem_size,
+                                     const bitrev_config_t* cfg, void* stream) {
+  if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;
+  return run_plain(src, dst, log2n, 1, elem_size, cfg, stream, false);
+}
+
+bitrev_status_t bitrev_rows(const void* src, void* dst, int log2n, int64_t rows,
+                            size_t elem_size, void* stream) {
+  return run_plain(src, dst, log2n, rows, elem_size, NULL, stream, true);
+}
+
+bitrev_status_t bitrev_rows_ex(const void* src, void* dst, int log2n, int64_t rows,
+                               size_t elem_size, const bitrev_config_t* cfg, void* stream) {
+  return run_plain(src, dst, log2n, rows, elem_size, cfg, stream, true);
+}
+
+size_t bitrev_batched_workspace_size(int64_t num_arrays) {
+  if (num_arrays < 0 || num_arrays > (1ll << 40)) return 0;
+  const size_t raw = ((size_t)num_arrays + 3) * 8;
+  return (raw + 255) / 256 * 256;
+}
+
+bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t* offsets,
+                                  const int32_t* log2n, int64_t num_arrays, size_t elem_size,
+                                  void* workspace, size_t workspace_bytes,
+                                  const bitrev_config_t* cfg, void* stream) {
+  // ---- validation: no HIP call before this block completes ----
+  if (num_arrays < 0 || num_arrays > (1ll << 40) || data_elems < 0 || !valid_elem_size(elem_size) ||
+      !valid_config(cfg))
+    return BITREV_ERROR_INVALID_VALUE;
+  if (num_arrays == 0) return BITREV_SUCCESS;
+  if (data == NULL || offsets == NULL || log2n == NULL) return BITREV_ERROR_INVALID_VALUE;
+  if (reinterpret_cast<uintptr_t>(data) % elem_size || reinterpret_cast<uintptr_t>(offsets) % 8 ||
+      reinterpret_cast<uintptr_t>(log2n) % 4)
+    return BITREV_ERROR_INVALID_VALUE;
+  if (workspace == NULL || reinterpret_cast<uintptr_t>(workspace) % 8 ||
+      workspace_bytes < bitrev_batched_workspace_size(num_arrays))
+    return BITREV_ERROR_WORKSPACE;
+  // ---- plan and launch ----
+  DeviceInfo d;
+  bitrev_status_t st = device_info(&d, false);
+  if (st != BITREV_SUCCESS) return st;
+  Plan p;
+  st = plan_batched((int)elem_size, cfg, d, &p);
+  if (st != BITREV_SUCCESS) return st;
+  BatchedLaunch a;
+  a.data = data;
+  a.offsets = offsets;
+  a.log2n = log2n;
+  a.num = num_arrays;
+  a.data_elems = data_elems;
+  a.ws = static_cast<int64_t*>(workspace);
+  a.b = p.b;
+  a.balanced = p.order == 2 ? 1 : 0;
+  a.xcds = d.xcds;
+  a.grid = p.grid;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_batched_prep(a, hs);
+  if (e != hipSuccess) return hip_fail(e);
+  switch (elem_size) {
+    case 1: e = launch_batched_s1(a, hs); break;
+    case 2: e = launch_batched_s2(a, hs); break;
+    case 4: e = launch_batched_s4(a, hs); break;
+    case 8: e = launch_batched_s8(a, hs); break;
+    default: e = launch_batched_s16(a, hs); break;
+  }
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+bitrev_status_t bitrev_batched(void* data, int64_t data_elems, const int64_t* offsets,
+                               const int32_t* log2n, int64_t num_arrays, size_t elem_size,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+  return bitrev_batched_ex(data, data_elems, offsets, log2n, num_arrays, elem_size, workspace,
+                           workspace_bytes, NULL, stream);
+}
+
+bitrev_status_t bitrev_batched_errors(const void* workspace, int64_t* num_rejected,
+                                      int64_t* first_rejected, void* stream) {
+  if (workspace == NULL || reinterpret_cast<uintptr_t>(workspace) % 8) return BITREV_ERROR_WORKSPACE;
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  int64_t hdr[2] = {0, -1};
+  e = hipMemcpy(hdr, workspace, sizeof hdr, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  if (num_rejected) *num_rejected = hdr[0];
+  if (first_rejected) *first_rejected = hdr[1];
+  return BITREV_SUCCESS;
+}
+
+bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int mode,
+                                  const bitrev_config_t* cfg, bitrev_plan_t* plan) {
+  if (plan == NULL || mode < 0 || mode > 2 || !valid_elem_size(elem_size) || !valid_config(cfg) ||
+      rows < 0 || (mode != 2 && (log2n < 0 || log2n > BITREV_MAX_LOG2N)))
+    return BITREV_ERROR_INVALID_VALUE;
+  DeviceInfo d;
+  bitrev_status_t st = device_info(&d, true);
+  if (st != BITREV_SUCCESS) return st;
+  Plan p;
+  st = (mode == 2) ? plan_batched((int)elem_size, cfg, d, &p)
+                   : plan_plain(mode, log2n, (int)elem_size, rows, cfg, 16, d, &p);
+  if (st != BITREV_SUCCESS) return st;
+  memset(plan, 0, sizeof *plan);
+  plan->path = p.path;
+  plan->tile_bits = p.b;
+  plan->mid_bits = p.m;
+  plan->block_threads = p.threads;
+  plan->grid_blocks = (int)p.grid;
+  plan->order = p.order;
+  plan->vector_access = p.vec ? 1 : 0;
+  plan->work_items = p.total;
+  plan->lds_bytes = p.lds;
+  return BITREV_SUCCESS;
+}
+
+bitrev_status_t bitrev_load_tuning(const char* path) {
+  load_env_tuning();  // an explicit load always wins over the environment
+  return load_tuning_file(path);
+}
+
+const char* bitrev_tuning_format(void) { return kTuningFormat; }
+
+bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (src == NULL || dst == NULL) return BITREV_ERROR_INVALID_VALUE;
+  if (bytes == 0) return BITREV_SUCCESS;
+  if (overlap(src, dst, bytes)) return BITREV_ERROR_ALIAS;
+  DeviceInfo d;
+  bitrev_status_t st = device_info(&d, false);
+  if (st != BITREV_SUCCESS) return st;
+  const hipError_t e = launch_copy(src, dst, bytes, (uint32_t)(d.cus * 16),
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+const char* bitrev_status_string(bitrev_status_t status) {
+  switch (status) {
+    case BITREV_SUCCESS: return "success";
+    case BITREV_ERROR_INVALID_VALUE: return "invalid value";
+    case BITREV_ERROR_ALIAS: return "source and destination overlap";
+    case BITREV_ERROR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case BITREV_ERROR_HIP: return "HIP runtime error";
+    case BITREV_ERROR_NOT_SUPPORTED: return "not supported by this build or device";
+  }
+  return "unknown status";
+}
+
+int bitrev_last_hip_error(void) { return g_last_hip_error; }
+
+int bitrev_abi_version(void) { return BITREV_ABI_VERSION; }
+
+uint32_t bitrev_debug_rev(uint32_t v, int j) {
+  return (j < 0 || j > 32) ? 0u : rev_bits(v, j);
+}
+
+uint64_t bitrev_debug_pair_count(int m) { return (m < 0 || m > 32) ? 0 : pair_count(m); }
+
+uint32_t bitrev_debug_pair_at(int m, uint64_t w, int balanced) {
+  if (m < 0 || m > 32 || w >= pair_count(m)) return 0xFFFFFFFFu;
+  return pair_at(m, w, balanced != 0);
+}
+
+uint32_t bitrev_debug_spread(uint32_t w, int width) {
+  return (width < 0 || width > 32) ? 0u : spread_bits(w, width);
+}
+
+}  // extern "C"

@@ -1,0 +1,304 @@
+// Device-side building blocks of libbitrev: index reversal, the work-item
+// enumeration, and the per-work-item routines that the kernels in
+// bitrev_kernels.hip compose.  Written for gfx950 (64-lane wavefronts).
+//
+// The method (arXiv:1708.01873, Introduction, bit reversal using a matrix
+// buffer): split an index of k bits as i = [x | y | z] with x the high b bits,
+// y the middle m = k - 2b bits and z the low b bits.  Then
+// rev_k(i) = [rev_b(z) | rev_m(y) | rev_b(x)], so the 2^b x 2^b "tile" of
+// elements sharing the middle bits y (rows x, each a contiguous run of 2^b
+// elements z) lands as a whole on tile rev_m(y), with element (x, z) at row
+// rev_b(z), column rev_b(x).  Each tile is staged through LDS so that both the
+// HBM read (rows of the source tile) and the HBM write (rows of the
+// destination tile) move whole contiguous rows.
+//
+// In place, tiles y and rev_m(y) swap (the paper's in-place variant of the
+// buffered method, and the pairing by i < rev(i) of the Introduction's
+// listing).  One work item owns the pair {y, rev_m(y)} with y <= rev_m(y):
+// both tiles are read completely before the workgroup barrier and written
+// after it, and no other work item touches either tile, so the swap is
+// race-free without any global synchronisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bitrev {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// An opaque block of N bytes held in registers.
+template <int N> struct Bytes;
+template <> struct Bytes<1> { typedef uint8_t T; };
+template <> struct Bytes<2> { typedef uint16_t T; };
+template <> struct Bytes<4> { typedef uint32_t T; };
+template <> struct Bytes<8> { typedef u32x2 T; };
+template <> struct Bytes<16> { typedef u32x4 T; };
+
+// VB bytes seen either as one vector or as VB/S elements of S bytes.
+template <int S, int VB> union Chunk {
+  typename Bytes<VB>::T v;
+  typename Bytes<S>::T e[VB / S];
+};
+
+// Reverse the low j bits of v, 0 <= j <= 32 (v_bfrev_b32 and a shift).  The
+// 64-bit shift makes j = 0 yield 0, the reversal of the empty bit string.
+__host__ __device__ __forceinline__ uint32_t rev_bits(uint32_t v, int j) {
+  return (uint32_t)(((uint64_t)__builtin_bitreverse32(v)) >> (32 - j));
+}
+
+template <int J> __host__ __device__ __forceinline__ uint32_t rev_c(uint32_t v) {
+  if constexpr (J == 0) {
+    return 0u;
+  } else {
+    return __builtin_bitreverse32(v) >> (32 - J);
+  }
+}
+
+// Gather the even-position bits of w into the low half (bit 2t -> bit t).
+__host__ __device__ __forceinline__ uint32_t compact_even(uint32_t w) {
+  uint32_t x = w & 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+  x = (x | (x >> 4)) & 0x00FF00FFu;
+  x = (x | (x >> 8)) & 0x0000FFFFu;
+  return x;
+}
+
+// A bijection on width-bit values that deals the bits of w alternately to
+// the low end and the high end of the field: bit 0 -> 0, bit 1 -> width-1,
+// bit 2 -> 1, bit 3 -> width-2, ...  A run of consecutive w then varies both
+// the low and the high bits of the result, so that consecutive work items
+// touch tiles whose reversal partners are spread over HBM channels too.
+__host__ __device__ __forceinline__ uint32_t spread_bits(uint32_t w, int width) {
+  return compact_even(w) | rev_bits(compact_even(w >> 1), width);
+}
+
+// Number of y in [0, 2^m) with y <= rev_m(y): the r(m) swapping pairs plus
+// the 2^ceil(m/2) palindromes, (2^m + 2^ceil(m/2)) / 2.
+__host__ __device__ __forceinline__ uint64_t pair_count(int m) {
+  return ((1ull << m) + (1ull << ((m + 1) / 2))) >> 1;
+}
+
+// The w-th y (0 <= w < pair_count(m)) with y <= rev_m(y).  Bits are decided
+// from the outside in, as in the paper's branch-and-bound enumeration of
+// swap pairs (Methods, unrolling): an outer pair (top, bottom) = (0, 1) makes
+// y < rev(y) whatever the inner bits are; (1, 0) never qualifies; equal outer
+// bits defer to the inner m - 2 bits.  Counting the three cases gives
+// pair_count(m) = 2^(m-2) + 2 pair_count(m-2).  When `balanced`, the free
+// inner bits are dealt by spread_bits instead of in natural order.
+__host__ __device__ __forceinline__ uint32_t pair_at(int m, uint64_t w, bool balanced) {
+  uint32_t y = 0;
+  int lo = 0;
+  int width = m;
+  while (width >= 2) {
+    const uint64_t q = 1ull << (width - 2);
+    if (w < q) {
+      uint32_t u = (uint32_t)w;
+      if (balanced) u = spread_bits(u, width - 2);
+      return y | (1u << lo) | (u << (lo + 1));
+    }
+    w -= q;
+    if (w & 1) y |= (1u << lo) | (1u << (lo + width - 1));
+    w >>= 1;
+    lo += 1;
+    width -= 2;
+  }
+  if (width == 1) y |= (uint32_t)(w & 1) << lo;
+  return y;
+}
+
+// LDS padding per tile row, in elements: one element (at least 4 bytes)
+// staggers consecutive rows across banks for the column-wise scatter.
+__host__ __device__ constexpr int lds_pad_elems(int s) { return s >= 4 ? 1 : 4 / s; }
+
+// LDS bytes of `tiles` staged tiles of width b for s-byte elements.
+__host__ __device__ constexpr size_t tile_lds_bytes_for(int s, int b, int tiles) {
+  return (size_t)tiles * ((size_t)1 << b) * (((size_t)1 << b) + (size_t)lds_pad_elems(s)) * (size_t)s;
+}
+
+// The tile geometry for element size S, tile width B and access mode.
+// VEC: global memory moves 16-byte vectors (or whole rows, if shorter);
+// otherwise one element per access (used when a base pointer is not
+// 16-byte aligned).
+template <int S, int B, bool VEC> struct TileShape {
+  static constexpr int R = 1 << B;                  // rows per tile = elements per row
+  static constexpr int ROWB = R * S;                // bytes per row
+  static constexpr int VB = VEC ? (ROWB < 16 ? ROWB : 16) : S;  // bytes per access
+  static constexpr int CE = VB / S;                 // elements per access
+  static constexpr int CPR = R / CE;                // accesses per row
+  static constexpr int CPT = R * CPR;               // accesses per tile
+  static constexpr int PADE = lds_pad_elems(S);
+  static constexpr int PE = R + PADE;               // LDS row pitch, elements
+  static constexpr int TILE_E = R * PE;             // LDS elements per tile
+};
+
+// Threads per workgroup for a tile kernel: two accesses per thread per tile,
+// between one wavefront and 1024 threads.
+template <int S, int B, bool VEC> constexpr int tile_threads() {
+  constexpr int c = TileShape<S, B, VEC>::CPT / 2;
+  return c < 64 ? 64 : (c > 1024 ? 1024 : c);
+}
+
+// Logical block index: the hardware deals workgroups to the XCDs round
+// robin, so block i runs on XCD i % xcds.  Renumber so that each XCD owns a
+// contiguous range of work items; neighbouring work items then share its L2
+// and spread over its channels.  grid must be a multiple of xcds.
+__device__ __forceinline__ uint32_t xcd_block(int xcds) {
+  const uint32_t g = gridDim.x / (uint32_t)xcds;
+  return (blockIdx.x % (uint32_t)xcds) * g + blockIdx.x / (uint32_t)xcds;
+}
+
+// ---------------------------------------------------------------------------
+// Tile routines.  All threads of the workgroup call them together; `lds`
+// holds room for two tiles.
+// ---------------------------------------------------------------------------
+
+// Load one tile (middle bits y) of the array at `base` into registers.
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void tile_load(Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                          const typename Bytes<S>::T* __restrict__ base,
+                                          uint64_t rowstride, uint32_t y) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<Sh::VB>::T V;
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    if (Sh::CPT % NT == 0 || q < Sh::CPT) {
+      const int x = q / Sh::CPR;
+      const int zc = q % Sh::CPR;
+      const uint64_t off = (uint64_t)x * rowstride + (uint64_t)y * Sh::R + (uint64_t)(zc * Sh::CE);
+      reg[i].v = *reinterpret_cast<const V*>(base + off);
+    }
+  }
+}
+
+// Scatter registers into LDS in destination order: source (x, z) goes to
+// LDS row rev_b(z), column rev_b(x).
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void tile_scatter(const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                             typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    if (Sh::CPT % NT == 0 || q < Sh::CPT) {
+      const int x = q / Sh::CPR;
+      const int zc = q % Sh::CPR;
+      const uint32_t col = rev_c<B>((uint32_t)x);
+#pragma unroll
+      for (int j = 0; j < Sh::CE; ++j) {
+        const uint32_t row = rev_c<B>((uint32_t)(zc * Sh::CE + j));
+        lds[row * Sh::PE + col] = reg[i].e[j];
+      }
+    }
+  }
+}
+
+// Write the staged tile (destination order in LDS) to tile y of `base`.
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void tile_store(typename Bytes<S>::T* __restrict__ base,
+                                           uint64_t rowstride, uint32_t y,
+                                           const typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<Sh::VB>::T V;
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    if (Sh::CPT % NT == 0 || q < Sh::CPT) {
+      const int r = q / Sh::CPR;
+      const int cc = q % Sh::CPR;
+      Chunk<S, Sh::VB> c;
+#pragma unroll
+      for (int j = 0; j < Sh::CE; ++j) c.e[j] = lds[r * Sh::PE + cc * Sh::CE + j];
+      const uint64_t off = (uint64_t)r * rowstride + (uint64_t)y * Sh::R + (uint64_t)(cc * Sh::CE);
+      *reinterpret_cast<V*>(base + off) = c.v;
+    }
+  }
+}
+
+// In place: swap tiles y and yr = rev_m(y) of the array at `base` (one tile
+// when y is a palindrome).  Ends with the LDS free for the next item only
+// after the caller's barrier.
+template <int S, int B, bool VEC, int NT>
+__device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restrict__ base, int m,
+                                                  uint32_t y, typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  const uint64_t rowstride = 1ull << (m + B);
+  const uint32_t yr = rev_bits(y, m);
+  const bool pal = (yr == y);
+  Chunk<S, Sh::VB> ra[PT], rb[PT];
+  tile_load<S, B, VEC, NT, PT>(ra, base, rowstride, y);
+  if (!pal) tile_load<S, B, VEC, NT, PT>(rb, base, rowstride, yr);
+  tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+  if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+  __syncthreads();
+  tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
+  if (!pal) tile_store<S, B, VEC, NT, PT>(base, rowstride, y, lds + Sh::TILE_E);
+}
+
+// Out of place: tile y of `src` to tile rev_m(y) of `dst`.
+template <int S, int B, bool VEC, int NT>
+__device__ __forceinline__ void tile_outofplace(const typename Bytes<S>::T* __restrict__ src,
+                                                typename Bytes<S>::T* __restrict__ dst, int m,
+                                                uint32_t y, typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  const uint64_t rowstride = 1ull << (m + B);
+  Chunk<S, Sh::VB> ra[PT];
+  tile_load<S, B, VEC, NT, PT>(ra, src, rowstride, y);
+  tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+  __syncthreads();
+  tile_store<S, B, VEC, NT, PT>(dst, rowstride, rev_bits(y, m), lds);
+}
+
+// ---------------------------------------------------------------------------
+// Whole array in one workgroup's LDS (any 2^k that fits): load, barrier,
+// out[i] = lds[rev_k(i)].  One element per access; the padding of one
+// element every 32 breaks the power-of-two strides of the gather.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t small_slot(uint32_t i) { return i + (i >> 5); }
+
+template <int S, int NT>
+__device__ __forceinline__ void small_array(const typename Bytes<S>::T* src,
+                                            typename Bytes<S>::T* dst, int k,
+                                            typename Bytes<S>::T* lds) {
+  const uint32_t n = 1u << k;
+  for (uint32_t i = threadIdx.x; i < n; i += NT) lds[small_slot(i)] = src[i];
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += NT) dst[i] = lds[small_slot(rev_bits(i, k))];
+}
+
+// ---------------------------------------------------------------------------
+// Whole array in one wavefront (n = 2^k <= 64): lane i holds element i and
+// fetches element rev_k(i) from its lane with ds_bpermute, one dword at a
+// time.  No LDS storage and no barrier.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ void wave_array(const typename Bytes<S>::T* src,
+                                           typename Bytes<S>::T* dst, int k, int lane) {
+  typedef typename Bytes<S>::T E;
+  const int n = 1 << k;
+  const bool live = lane < n;
+  const int from = (int)rev_bits((uint32_t)lane, k) * 4;
+  E v;
+  if constexpr (S <= 4) {
+    v = live ? src[lane] : (E)0;
+    const uint32_t w = __builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)v);
+    if (live) dst[lane] = (E)w;
+  } else {
+    if (live) {
+      v = src[lane];
+    } else {
+      v = (E)0u;
+    }
+    E out;
+#pragma unroll
+    for (int d = 0; d < S / 4; ++d) out[d] = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)v[d]);
+    if (live) dst[lane] = out;
+  }
+}
+
+}  // namespace bitrev

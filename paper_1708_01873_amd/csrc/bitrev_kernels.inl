@@ -1,0 +1,204 @@
+// Kernels of libbitrev, instantiated for one element size BITREV_S per
+// translation unit (bitrev_s<S>.hip includes this file).
+#include "bitrev_device.hpp"
+#include "bitrev_launch.hpp"
+
+#ifndef BITREV_S
+#error "define BITREV_S (element size in bytes) before including bitrev_kernels.inl"
+#endif
+
+namespace bitrev {
+namespace {
+
+// In place, one array or `total_items / items_per_seg` equal arrays: work
+// item -> (array, pair y <= rev_m(y)) -> swap the two tiles through LDS.
+template <int S, int B, bool VEC>
+__global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace(
+    void* data, int m, uint64_t items_per_seg, uint64_t total_items, uint64_t seg_elems,
+    int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  constexpr int NT = tile_threads<S, B, VEC>();
+  __shared__ E lds[2 * TileShape<S, B, VEC>::TILE_E];
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    uint64_t seg = 0, local = item;
+    if (items_per_seg != total_items) {
+      seg = item / items_per_seg;
+      local = item - seg * items_per_seg;
+    }
+    const uint32_t y = pair_at(m, local, balanced != 0);
+    tile_pair_inplace<S, B, VEC, NT>(static_cast<E*>(data) + seg * seg_elems, m, y, lds);
+    __syncthreads();
+  }
+}
+
+// Out of place: work item -> (array, tile y) -> tile rev_m(y) of dst.
+template <int S, int B, bool VEC>
+__global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace(
+    const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
+    uint64_t seg_elems, int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  constexpr int NT = tile_threads<S, B, VEC>();
+  __shared__ E lds[TileShape<S, B, VEC>::TILE_E];
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    uint64_t seg = 0, local = item;
+    if (items_per_seg != total_items) {
+      seg = item / items_per_seg;
+      local = item - seg * items_per_seg;
+    }
+    const uint32_t y = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
+    tile_outofplace<S, B, VEC, NT>(static_cast<const E*>(src) + seg * seg_elems,
+                                   static_cast<E*>(dst) + seg * seg_elems, m, y, lds);
+    __syncthreads();
+  }
+}
+
+// n = 2^k <= 64: one wavefront per array, four arrays per workgroup.
+template <int S>
+__global__ __launch_bounds__(256) void k_wave(const void* src, void* dst, int k, uint64_t nseg) {
+  typedef typename Bytes<S>::T E;
+  const int lane = (int)(threadIdx.x & 63u);
+  const uint64_t n = 1ull << k;
+  for (uint64_t seg = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); seg < nseg;
+       seg += (uint64_t)gridDim.x * 4) {
+    wave_array<S>(static_cast<const E*>(src) + seg * n, static_cast<E*>(dst) + seg * n, k, lane);
+  }
+}
+
+// Largest a in [0, num) with scan[a] <= item, for non-decreasing scan with
+// scan[0] <= item < scan[num].  Each round the 64 lanes probe 63 evenly
+// spaced entries; the number that are <= item (a prefix) narrows the range
+// 64-fold.  Every lane of the wavefront ends with the same answer.
+__device__ __forceinline__ int64_t find_array(const int64_t* scan, int64_t num, uint64_t item) {
+  const int lane = (int)(threadIdx.x & 63u);
+  int64_t lo = 0, hi = num;
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t idx = lo + (int64_t)(lane + 1) * step;
+    const bool pred = idx < hi && (uint64_t)scan[idx] <= item;
+    const int cnt = __popcll(__ballot(pred));
+    lo += (int64_t)cnt * step;
+    hi = (lo + step < hi) ? lo + step : hi;
+  }
+  return lo;
+}
+
+// Batched, in place, persistent: the prep kernel has written the exclusive
+// scan of per-array work counts to ws[2..]; every workgroup walks the global
+// work ids with a grid stride, finds its array and runs either the
+// whole-array LDS routine (2^k < 2^(2b)) or one tile pair at width b.
+template <int S, int B>
+__global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched(
+    void* data, const int64_t* offsets, const int32_t* log2n, int64_t num, const int64_t* ws,
+    int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  constexpr int NT = tile_threads<S, B, true>();
+  __shared__ E lds[2 * TileShape<S, B, true>::TILE_E];
+  const int64_t* scan = ws + 2;
+  const uint64_t total = (uint64_t)scan[num];
+  for (uint64_t item = xcd_block(xcds); item < total; item += gridDim.x) {
+    const int64_t a = find_array(scan, num, item);
+    const int k = log2n[a];
+    E* base = static_cast<E*>(data) + offsets[a];
+    if (k < 2 * B) {
+      small_array<S, NT>(base, base, k, lds);
+    } else {
+      const int m = k - 2 * B;
+      const uint32_t y = pair_at(m, item - (uint64_t)scan[a], balanced != 0);
+      if ((reinterpret_cast<uintptr_t>(base) & 15u) == 0) {
+        tile_pair_inplace<S, B, true, NT>(base, m, y, lds);
+      } else {
+        tile_pair_inplace<S, B, false, NT>(base, m, y, lds);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int S, int B, bool VEC>
+hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_tile_inplace<S, B, VEC>), dim3(a.grid), dim3(tile_threads<S, B, VEC>()),
+                     0, st, a.dst, a.m, a.items_per_seg, a.total_items, a.seg_elems, a.balanced,
+                     a.xcds);
+  return hipGetLastError();
+}
+
+template <int S, int B, bool VEC>
+hipError_t run_tile_outofplace(const TileLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC>), dim3(a.grid),
+                     dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
+                     a.total_items, a.seg_elems, a.balanced, a.xcds);
+  return hipGetLastError();
+}
+
+template <int S, int B>
+hipError_t run_batched(const BatchedLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_batched<S, B>), dim3(a.grid), dim3(tile_threads<S, B, true>()), 0, st,
+                     a.data, a.offsets, a.log2n, a.num, (const int64_t*)a.ws, a.balanced, a.xcds);
+  return hipGetLastError();
+}
+
+// Dispatch a runtime tile width onto the compiled instantiations.
+template <int S, int B = 0>
+hipError_t dispatch_tile(bool inplace, int b, bool vec, const TileLaunch& a, hipStream_t st) {
+  if constexpr (B > max_tile_bits(S)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (b == B) {
+      if (inplace) return vec ? run_tile_inplace<S, B, true>(a, st) : run_tile_inplace<S, B, false>(a, st);
+      return vec ? run_tile_outofplace<S, B, true>(a, st) : run_tile_outofplace<S, B, false>(a, st);
+    }
+    return dispatch_tile<S, B + 1>(inplace, b, vec, a, st);
+  }
+}
+
+template <int S, int B = kMinBatchedTileBits>
+hipError_t dispatch_batched(const BatchedLaunch& a, hipStream_t st) {
+  if constexpr (B > max_tile_bits(S)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.b == B) return run_batched<S, B>(a, st);
+    return dispatch_batched<S, B + 1>(a, st);
+  }
+}
+
+template <int S, int B = 0>
+int threads_for(int b, bool vec) {
+  if constexpr (B > max_tile_bits(S)) {
+    return 0;
+  } else {
+    if (b == B) return vec ? tile_threads<S, B, true>() : tile_threads<S, B, false>();
+    return threads_for<S, B + 1>(b, vec);
+  }
+}
+
+}  // namespace
+
+#define BITREV_CAT2(a, b) a##b
+#define BITREV_CAT(a, b) BITREV_CAT2(a, b)
+
+hipError_t BITREV_CAT(launch_tile_inplace_s, BITREV_S)(int b, bool vec, const TileLaunch& a,
+                                                       hipStream_t st) {
+  return dispatch_tile<BITREV_S>(true, b, vec, a, st);
+}
+
+hipError_t BITREV_CAT(launch_tile_outofplace_s, BITREV_S)(int b, bool vec, const TileLaunch& a,
+                                                          hipStream_t st) {
+  return dispatch_tile<BITREV_S>(false, b, vec, a, st);
+}
+
+hipError_t BITREV_CAT(launch_wave_s, BITREV_S)(const WaveLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_wave<BITREV_S>), dim3(a.grid), dim3(256), 0, st, a.src, a.dst, a.k, a.nseg);
+  return hipGetLastError();
+}
+
+hipError_t BITREV_CAT(launch_batched_s, BITREV_S)(const BatchedLaunch& a, hipStream_t st) {
+  return dispatch_batched<BITREV_S>(a, st);
+}
+
+int BITREV_CAT(tile_threads_s, BITREV_S)(int b, bool vec) { return threads_for<BITREV_S>(b, vec); }
+
+int BITREV_CAT(batched_threads_s, BITREV_S)(int b) {
+  return b < kMinBatchedTileBits ? 0 : threads_for<BITREV_S>(b, true);
+}
+
+}  // namespace bitrev

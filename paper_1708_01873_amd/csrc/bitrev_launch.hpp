@@ -1,0 +1,78 @@
+// Host-side interface between the C ABI (bitrev_api.hip) and the kernels.
+// One translation unit per element size instantiates the kernels for that
+// size (bitrev_s<S>.hip) and defines the launchers declared here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bitrev {
+
+constexpr int kMaxTileBits = 7;
+
+// Largest tile width b compiled for element size s.
+constexpr int max_tile_bits(int s) { return s >= 8 ? 6 : 7; }
+
+// Smallest tile width the batched kernel is compiled for.
+constexpr int kMinBatchedTileBits = 2;
+
+struct TileLaunch {
+  const void* src;          // source array(s)
+  void* dst;                // destination array(s); == src for in place
+  int m;                    // middle bits: log2n - 2b
+  uint64_t items_per_seg;   // work items per array
+  uint64_t total_items;     // items_per_seg * number of arrays
+  uint64_t seg_elems;       // elements between consecutive arrays (2^log2n)
+  int balanced;             // work-item order: 0 natural, 1 balanced bit dealing
+  int xcds;                 // number of XCDs the grid is dealt over
+  uint32_t grid;            // workgroups (multiple of xcds)
+};
+
+struct WaveLaunch {
+  const void* src;
+  void* dst;
+  int k;                    // log2n <= 6
+  uint64_t nseg;            // number of arrays
+  uint32_t grid;
+};
+
+struct BatchedLaunch {
+  void* data;
+  const int64_t* offsets;
+  const int32_t* log2n;
+  int64_t num;
+  int64_t data_elems;
+  int64_t* ws;              // [0] invalid count, [1] first invalid, [2..] scan
+  int b;
+  int balanced;
+  int xcds;
+  uint32_t grid;
+};
+
+// Threads per workgroup of the tile kernels for (s, b, vec); 0 if not built.
+int tile_block_threads(int s, int b, bool vec);
+// Threads per workgroup of the batched kernel for (s, b).
+int batched_block_threads(int s, int b);
+// Static LDS bytes per workgroup of each kernel (for occupancy estimates).
+size_t tile_lds_bytes(int s, int b, bool inplace);
+
+#define BITREV_DECLARE_LAUNCHERS(S)                                                  \
+  hipError_t launch_tile_inplace_s##S(int b, bool vec, const TileLaunch& a,          \
+                                      hipStream_t st);                               \
+  hipError_t launch_tile_outofplace_s##S(int b, bool vec, const TileLaunch& a,       \
+                                         hipStream_t st);                            \
+  hipError_t launch_wave_s##S(const WaveLaunch& a, hipStream_t st);                  \
+  hipError_t launch_batched_s##S(const BatchedLaunch& a, hipStream_t st);            \
+  int tile_threads_s##S(int b, bool vec);                                            \
+  int batched_threads_s##S(int b);
+
+BITREV_DECLARE_LAUNCHERS(1)
+BITREV_DECLARE_LAUNCHERS(2)
+BITREV_DECLARE_LAUNCHERS(4)
+BITREV_DECLARE_LAUNCHERS(8)
+BITREV_DECLARE_LAUNCHERS(16)
+
+hipError_t launch_batched_prep(const BatchedLaunch& a, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, uint32_t grid, hipStream_t st);
+
+}  // namespace bitrev

@@ -1,0 +1,221 @@
+"""The C ABI on the host: symbols, argument validation, plans, tuning files and
+the kernels' index arithmetic (host build of the same source).  No GPU needed:
+every call here either fails validation before any HIP call or is host-only.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1708_01873_amd as br
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(br.LIBRARY):
+        import __graft_entry__
+        __graft_entry__.build()
+    return br.lib()
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "bitrev.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(bitrev_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(L):
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(br.EXPORTED)
+
+
+def test_abi_version_and_status_strings(L):
+    assert br.abi_version() == 1
+    for st in range(6):
+        assert br.status_string(st)
+    assert br.status_string(99) == "unknown status"
+
+
+FAKE = 1 << 20  # a nonzero, 16-byte aligned address never dereferenced
+
+
+@pytest.mark.parametrize("args,want", [
+    ((None, 10, 4), br.ERROR_INVALID_VALUE),
+    ((FAKE, -1, 4), br.ERROR_INVALID_VALUE),
+    ((FAKE, 41, 4), br.ERROR_INVALID_VALUE),
+    ((FAKE, 10, 3), br.ERROR_INVALID_VALUE),
+    ((FAKE, 10, 0), br.ERROR_INVALID_VALUE),
+    ((FAKE, 10, 32), br.ERROR_INVALID_VALUE),
+    ((FAKE + 2, 10, 4), br.ERROR_INVALID_VALUE),
+    ((FAKE + 8, 10, 16), br.ERROR_INVALID_VALUE),
+])
+def test_inplace_validation(L, args, want):
+    assert L.bitrev_inplace(args[0], args[1], args[2], None) == want
+
+
+def test_trivial_inplace_needs_no_device(L):
+    # n = 1 and n = 2 are the identity: success without touching HIP
+    assert L.bitrev_inplace(FAKE, 0, 8, None) == br.SUCCESS
+    assert L.bitrev_inplace(FAKE, 1, 8, None) == br.SUCCESS
+
+
+def test_outofplace_validation(L):
+    n4 = 4 << 10
+    assert L.bitrev_outofplace(FAKE, FAKE, 10, 4, None) == br.ERROR_ALIAS
+    assert L.bitrev_outofplace(FAKE, FAKE + n4 - 4, 10, 4, None) == br.ERROR_ALIAS
+    assert L.bitrev_outofplace(FAKE + n4 - 4, FAKE, 10, 4, None) == br.ERROR_ALIAS
+    assert L.bitrev_outofplace(None, FAKE, 10, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_outofplace(FAKE, None, 10, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_outofplace(FAKE, FAKE + n4 + 2, 10, 4, None) == br.ERROR_INVALID_VALUE
+
+
+def test_rows_validation(L):
+    assert L.bitrev_rows(FAKE, FAKE + 4096, 10, -1, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_rows(FAKE, FAKE + 4096, 10, 0, 4, None) == br.SUCCESS
+    # two rows of 4 KiB overlap a destination 4 KiB further on
+    assert L.bitrev_rows(FAKE, FAKE + 4096, 10, 2, 4, None) == br.ERROR_ALIAS
+    # absurd sizes are rejected rather than overflowing
+    assert L.bitrev_rows(FAKE, FAKE, 40, 1 << 30, 16, None) == br.ERROR_INVALID_VALUE
+
+
+def test_config_validation(L):
+    for cfg in (br.Config(8, 0, 0, 0), br.Config(-1, 0, 0, 0), br.Config(0, -5, 0, 0),
+                br.Config(0, 0, 3, 0), br.Config(0, 0, 0, 1)):
+        assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
+
+
+def test_batched_validation(L):
+    ws = br.bitrev_batched_workspace_size(4096)
+    assert ws >= (4096 + 3) * 8 and ws % 256 == 0
+    assert br.bitrev_batched_workspace_size(-1) == 0
+    args = dict(data=FAKE, elems=1 << 20, off=FAKE, l2=FAKE, num=4096, s=8, ws=FAKE, wsb=ws)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return L.bitrev_batched(a["data"], a["elems"], a["off"], a["l2"], a["num"], a["s"],
+                                a["ws"], a["wsb"], None)
+
+    assert call(num=0) == br.SUCCESS
+    assert call(num=-1) == br.ERROR_INVALID_VALUE
+    assert call(data=None) == br.ERROR_INVALID_VALUE
+    assert call(off=None) == br.ERROR_INVALID_VALUE
+    assert call(l2=None) == br.ERROR_INVALID_VALUE
+    assert call(s=12) == br.ERROR_INVALID_VALUE
+    assert call(elems=-1) == br.ERROR_INVALID_VALUE
+    assert call(off=FAKE + 4) == br.ERROR_INVALID_VALUE
+    assert call(data=FAKE + 4) == br.ERROR_INVALID_VALUE
+    assert call(ws=None) == br.ERROR_WORKSPACE
+    assert call(ws=FAKE + 4) == br.ERROR_WORKSPACE
+    assert call(wsb=ws - 1) == br.ERROR_WORKSPACE
+
+
+def test_copy_validation(L):
+    assert L.bitrev_copy(FAKE, FAKE + 8, 16, None) == br.ERROR_ALIAS
+    assert L.bitrev_copy(None, FAKE, 16, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy(FAKE, FAKE + 64, 0, None) == br.SUCCESS
+
+
+def test_plan_query_defaults(L):
+    p = br.bitrev_plan_query(24, 8)
+    assert p["path"] == br.PATH_TILE and p["tile_bits"] == 5 and p["mid_bits"] == 14
+    assert p["work_items"] == (2**14 + 2**7) // 2
+    assert p["grid_blocks"] % 8 == 0
+    p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
+    assert p["work_items"] == 2**14
+    p = br.bitrev_plan_query(5, 4)
+    assert p["path"] == br.PATH_WAVE
+    p = br.bitrev_plan_query(1, 4)
+    assert p["path"] == br.PATH_NONE
+    p = br.bitrev_plan_query(9, 8)  # small k: b shrinks to floor(k/2)
+    assert p["path"] == br.PATH_TILE and p["tile_bits"] == 4 and p["mid_bits"] == 1
+    p = br.bitrev_plan_query(16, 4, rows=256, mode=br.MODE_OUTOFPLACE)
+    assert p["work_items"] == 256 * 2 ** (16 - 2 * p["tile_bits"])
+    for b in (4, 5, 6):
+        p = br.bitrev_plan_query(24, 8, tile_bits=b)
+        assert p["tile_bits"] == b and p["mid_bits"] == 24 - 2 * b
+    with pytest.raises(br.BitrevError):
+        br.bitrev_plan_query(24, 8, tile_bits=7)  # not compiled for 8-byte elements
+    with pytest.raises(br.BitrevError):
+        br.bitrev_plan_query(8, 8, tile_bits=5)  # 2b > k
+    p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
+    assert p["path"] == br.PATH_BATCHED and p["grid_blocks"] % 8 == 0
+
+
+def test_tuning_file(L, tmp_path):
+    good = tmp_path / "tune.txt"
+    good.write_text("# comment\n\ninplace 8 24 6 0 2   # trailing comment\n"
+                    "batched 8 -1 4 4 1\n")
+    br.bitrev_load_tuning(str(good))
+    try:
+        assert br.bitrev_plan_query(24, 8)["tile_bits"] == 6
+        assert br.bitrev_plan_query(22, 8)["tile_bits"] == 5  # no entry: default
+        p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
+        assert p["tile_bits"] == 4 and p["order"] == 1 and p["grid_blocks"] == 4 * 256
+        for bad in ("inplace 8 24 6 0\n", "sideways 8 24 6 0 2\n", "inplace 3 24 6 0 2\n",
+                    "inplace 8 24 9 0 2\n", "inplace 8 24 6 0 2 7\n"):
+            f = tmp_path / "bad.txt"
+            f.write_text(bad)
+            with pytest.raises(br.BitrevError):
+                br.bitrev_load_tuning(str(f))
+            # a rejected file leaves the loaded table in place
+            assert br.bitrev_plan_query(24, 8)["tile_bits"] == 6
+        with pytest.raises(br.BitrevError):
+            br.bitrev_load_tuning(str(tmp_path / "missing.txt"))
+    finally:
+        br.bitrev_load_tuning(None)
+    assert br.bitrev_plan_query(24, 8)["tile_bits"] == 5
+    assert "tuning" in br.bitrev_tuning_format()
+
+
+def test_kernel_rev_matches_oracle(L):
+    rng = np.random.default_rng(21)
+    for j in range(0, 33):
+        for v in list(rng.integers(0, 2**32, size=64, dtype=np.uint64)) + [0, 2**32 - 1]:
+            v = int(v) & ((1 << j) - 1) if j < 32 else int(v)
+            assert L.bitrev_debug_rev(v, j) == oracle.rev(v, j), (v, j)
+
+
+@pytest.mark.parametrize("m", list(range(0, 17)))
+@pytest.mark.parametrize("balanced", [0, 1])
+def test_pair_enumeration_is_a_bijection(L, m, balanced):
+    """The kernels' work items cover every tile pair {y, rev(y)} exactly once:
+    the enumeration hits each y with y <= rev_m(y) once and nothing else."""
+    count = L.bitrev_debug_pair_count(m)
+    assert count == (2**m + 2 ** ((m + 1) // 2)) // 2
+    ys = np.array([L.bitrev_debug_pair_at(m, w, balanced) for w in range(count)], dtype=np.int64)
+    assert len(np.unique(ys)) == count
+    revs = oracle.rev_table(m)
+    assert np.all(ys < 2**m)
+    assert np.all(ys <= revs[ys])
+    assert count == int(np.count_nonzero(np.arange(2**m) <= revs))
+    assert L.bitrev_debug_pair_at(m, count, balanced) == 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("m", [20, 27, 32])
+def test_pair_enumeration_large_m_sampled(L, m):
+    rng = np.random.default_rng(m)
+    count = L.bitrev_debug_pair_count(m)
+    for w in list(rng.integers(0, count, size=2000)) + [0, count - 1]:
+        for bal in (0, 1):
+            y = L.bitrev_debug_pair_at(m, int(w), bal)
+            assert y < 2**m and y <= oracle.rev(y, m)
+
+
+@pytest.mark.parametrize("width", list(range(0, 15)) + [31, 32])
+def test_spread_is_a_bijection(L, width):
+    if width <= 14:
+        vals = [L.bitrev_debug_spread(w, width) for w in range(1 << width)]
+        assert sorted(vals) == list(range(1 << width))
+    # the dealing order: bit 2t -> t, bit 2t+1 -> width-1-t
+    for t in range(width):
+        want = (t // 2) if t % 2 == 0 else (width - 1 - t // 2)
+        assert L.bitrev_debug_spread(1 << t, width) == 1 << want, (width, t)

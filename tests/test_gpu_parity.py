@@ -1,0 +1,166 @@
+"""HIP path vs the CPU oracle, byte for byte, through the C ABI.
+
+Sizes span single tiles, several tiles and every code path (wave shuffle,
+tiles at every compiled width, both work orders, 16-byte and per-element
+global access); every comparison is exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1708_01873_amd as br
+from gpu_util import assert_bytes_equal, to_device, to_host_bytes
+from paper_1708_01873_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ELEM_SIZES = (1, 2, 4, 8, 16)
+MAX_B = {1: 7, 2: 7, 4: 7, 8: 6, 16: 6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    br.lib()
+
+
+def _run(host: np.ndarray, k: int, s: int, inplace: bool, pad_front: int = 0, **cfg):
+    """Run the library on `host` bytes and return the result bytes."""
+    x = to_device(host, s, pad_front)
+    if inplace:
+        br.bitrev_inplace(x, k, **cfg)
+        return to_host_bytes(x)
+    y = to_device(np.zeros_like(host), s, pad_front)
+    br.bitrev_outofplace(x, y, k, **cfg)
+    out = to_host_bytes(y)
+    assert_bytes_equal(to_host_bytes(x), host, "out-of-place modified its source")
+    return out
+
+
+def test_c1_uint32_n1024():
+    """uint32, n = 2^10, seeded uniform values and the identity array."""
+    for seed in (workloads.SEEDS["c1"],) + workloads.EXTRA_PARITY_SEEDS:
+        host = workloads.uint32_uniform(10, seed)
+        want = oracle.outofplace(host)
+        for inplace in (True, False):
+            assert_bytes_equal(_run(host, 10, 4, inplace), want, "c1 seed %d" % seed)
+    io = workloads.iota(10)
+    want = oracle.outofplace(io)
+    got = _run(io, 10, 4, True).view(np.uint32)
+    assert_bytes_equal(got, want, "iota")
+    assert all(int(got[j]) == oracle.rev(j, 10) for j in range(1024))
+
+
+@pytest.mark.parametrize("s", ELEM_SIZES)
+def test_default_plan_every_k(s):
+    """Every k from 0 to 20 with the library's own plan (wave path for k <= 6,
+    tiles above), in place and out of place."""
+    for k in range(0, 21):
+        host = workloads.byte_pattern((1 << k) * s, seed=100 * s + k)
+        want = oracle.outofplace(host, s)
+        for inplace in (True, False):
+            assert_bytes_equal(_run(host, k, s, inplace), want, "s=%d k=%d ip=%s" % (s, k, inplace))
+
+
+@pytest.mark.parametrize("s", ELEM_SIZES)
+def test_forced_tile_widths(s):
+    """Every compiled tile width b, at k = 2b (one tile), 2b + 1 (palindromic
+    pairs only), 2b + 3 and 2b + 6 (many pairs), both work orders."""
+    for b in range(1, MAX_B[s] + 1):
+        for extra in (0, 1, 3, 6):
+            k = 2 * b + extra
+            if (1 << k) * s > (64 << 20):
+                continue
+            host = workloads.byte_pattern((1 << k) * s, seed=7 * k + b)
+            want = oracle.outofplace(host, s)
+            for order in (1, 2):
+                for inplace in (True, False):
+                    got = _run(host, k, s, inplace, tile_bits=b, order=order)
+                    assert_bytes_equal(got, want, "s=%d b=%d k=%d order=%d ip=%s"
+                                       % (s, b, k, order, inplace))
+
+
+@pytest.mark.parametrize("s", (1, 2, 4, 8))
+def test_element_aligned_base(s):
+    """A base pointer that is only elem_size aligned takes the per-element
+    access path and still matches."""
+    for k in (7, 10, 13, 16):
+        host = workloads.byte_pattern((1 << k) * s, seed=k)
+        want = oracle.outofplace(host, s)
+        for inplace in (True, False):
+            got = _run(host, k, s, inplace, pad_front=1)
+            assert_bytes_equal(got, want, "misaligned s=%d k=%d ip=%s" % (s, k, inplace))
+
+
+@pytest.mark.parametrize("grid", [8, 24, 64])
+def test_persistent_grid(grid):
+    """A small explicit grid makes every workgroup loop over many items."""
+    k, s = 18, 8
+    host = workloads.byte_pattern((1 << k) * s, seed=grid)
+    want = oracle.outofplace(host, s)
+    for inplace in (True, False):
+        for order in (1, 2):
+            got = _run(host, k, s, inplace, grid_blocks=grid, order=order)
+            assert_bytes_equal(got, want, "grid=%d ip=%s order=%d" % (grid, inplace, order))
+
+
+def test_guard_regions_untouched():
+    """Bytes before and after the array are never written."""
+    for s, k in ((4, 10), (8, 15), (16, 12), (1, 17), (8, 4)):
+        n = 1 << k
+        guard = 4096 // s
+        full = workloads.byte_pattern((n + 2 * guard) * s, seed=k)
+        t = to_device(full, s)
+        br.bitrev_inplace(t[guard:guard + n], k)
+        out = torch.empty_like(t[guard:guard + n])
+        br.bitrev_outofplace(t[guard:guard + n], out, k)
+        got = to_host_bytes(t)
+        inner = full[guard * s:(guard + n) * s]
+        assert_bytes_equal(got[:guard * s], full[:guard * s], "front guard")
+        assert_bytes_equal(got[(guard + n) * s:], full[(guard + n) * s:], "back guard")
+        assert_bytes_equal(got[guard * s:(guard + n) * s], oracle.outofplace(inner, s), "inner")
+        # out-of-place of the permuted array is the original again
+        assert_bytes_equal(to_host_bytes(out), inner, "involution")
+
+
+@pytest.mark.parametrize("s", (4, 8, 16))
+def test_involution_on_device(s):
+    """Applying the in-place permutation twice restores the input (every tile
+    pair swapped exactly once per call)."""
+    for k in (8, 11, 14, 17, 20):
+        host = workloads.byte_pattern((1 << k) * s, seed=k + s)
+        x = to_device(host, s)
+        ref = x.clone()
+        br.bitrev_inplace(x, k)
+        br.bitrev_inplace(x, k)
+        torch.cuda.synchronize()
+        assert torch.equal(x.view(torch.uint8), ref.view(torch.uint8)), (s, k)
+
+
+@pytest.mark.parametrize("s", ELEM_SIZES)
+def test_rows(s):
+    """Independent rows, in place and out of place, against the oracle row by
+    row; covers the wave path with many arrays."""
+    for k, rows in ((0, 5), (3, 7), (6, 130), (9, 3), (12, 17), (16, 2)):
+        host = workloads.byte_pattern((rows << k) * s, seed=k * 31 + rows)
+        want = oracle.rows(host, k, s)
+        x = to_device(host, s)
+        y = torch.empty_like(x)
+        br.bitrev_rows(x, y, k)
+        assert_bytes_equal(to_host_bytes(y), want, "rows oop s=%d k=%d" % (s, k))
+        br.bitrev_rows(x, x, k)
+        assert_bytes_equal(to_host_bytes(x), want, "rows ip s=%d k=%d" % (s, k))
+
+
+def test_special_float_bits():
+    """NaN payloads, signed zeros and denormals move as bits."""
+    vals = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.5, 5e-324, 1e308] * 128,
+                    dtype=np.float64)
+    bits = vals.view(np.uint64).copy()
+    bits[4::8] = 0x7FF8DEADBEEF0001
+    bits[5::8] = 0xFFF0000000000001
+    want = oracle.outofplace(bits)
+    for inplace in (True, False):
+        assert_bytes_equal(_run(bits.view(np.uint8), 10, 8, inplace), want, "float bits")
