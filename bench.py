@@ -2,10 +2,12 @@
 
 A step is one in-place bit-reversed permutation of 2^24 complex64 elements
 (128 MiB, real and imaginary parts N(0, 1) from seed 2), already resident in
-HBM, with the library's default plan.  Between steps a 1 GiB scratch write
-evicts the array from L2 and the 256 MiB Infinity Cache (outside the timed
-interval), so every step reads and writes HBM.  HIP events on the launch
-stream time each step.
+HBM, with the library's default plan.  Between steps (outside the timed
+interval) a kernel reads a 1 GiB scratch buffer, which evicts the array from
+the L2 caches and the 256 MiB Infinity Cache, so every step starts from HBM.
+The flush reads rather than writes: a written flush leaves up to 256 MiB of
+dirty lines whose write-back would then be charged to the timed step.  HIP
+events on the launch stream time each step.
 
 Prints one JSON line: the effective bandwidth 2 n s / t (GB/s), the roofline
 block of the tile kernel, the CPU oracle baseline, and context figures (copy
@@ -51,13 +53,14 @@ class Timer:
     def __init__(self, torch, flush: bool):
         self.torch = torch
         self.flush = flush
-        self.scratch = torch.empty(FLUSH_BYTES // 4, dtype=torch.int32, device="cuda") if flush else None
-        self.tick = 0
+        self.scratch = None
+        if flush:
+            self.scratch = torch.empty(FLUSH_BYTES // 4, dtype=torch.int32, device="cuda")
+            self.scratch.fill_(1)
 
     def _flush(self):
         if self.scratch is not None:
-            self.tick += 1
-            self.scratch.fill_(self.tick)
+            self.scratch.sum()
 
     def time(self, fn, reps: int, warmup: int = 1) -> list[float]:
         torch = self.torch
@@ -129,6 +132,15 @@ def batched_speedup(torch, br, reps: int):
     off = torch.from_numpy(offsets).cuda()
     l2 = torch.from_numpy(log2n).cuda()
     nbytes = 2.0 * total * 8
+    # autotune the batched plan on this batch (before capture; even number of
+    # runs per candidate, so the data is unchanged), then load the table
+    import tempfile
+    from paper_1708_01873_amd import tune
+    t0 = time.perf_counter()
+    tuned = tune.tune_batched(x, off, l2, reps=2)
+    table = tune.write_tuning([tuned], os.path.join(tempfile.mkdtemp(), "batched_tuning.txt"))
+    br.bitrev_load_tuning(table)
+    tune_s = time.perf_counter() - t0
     g = BatchedGraph(x, off, l2)
     views = [x[int(offsets[a]):int(offsets[a + 1])] for a in range(4096)]
     ptrs = [(v.data_ptr(), int(log2n[a])) for a, v in enumerate(views)]
@@ -150,11 +162,16 @@ def batched_speedup(torch, br, reps: int):
     t_graph = timer.time(g.replay, reps)
     t_loop = timer.time(loop, reps)
     t_loopg = timer.time(loop_graph.replay, reps)
+    br.bitrev_load_tuning(None)
     med = statistics.median
     return {
         "workload": "4096 complex64 arrays, log2n uniform [8,20], seed 5",
         "elements": total,
         "plan": g.plan,
+        "autotune": {"seconds": round(tune_s, 2), "best": {
+            "tile_bits": tuned.best.tile_bits, "order": tuned.best.order,
+            "wg_per_cu": tuned.best.wg_per_cu, "ms": tuned.best.ms},
+            "candidates": len(tuned.ranking), "gain_over_builtin": round(tuned.gain_over_default, 3)},
         "graph_ms": med(t_graph),
         "graph_GBps": gbs(nbytes, med(t_graph)),
         "eager_loop_ms": med(t_loop),
@@ -174,6 +191,9 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline steps (for profiler runs)")
     ap.add_argument("--hot", action="store_true", help="do not flush caches between steps")
+    ap.add_argument("--tile-bits", type=int, default=0, help="force b (0: library plan)")
+    ap.add_argument("--variant", type=int, default=0, help="force the tile kernel variant")
+    ap.add_argument("--order", type=int, default=0, help="force the work-item order")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU form is a design "
@@ -198,11 +218,12 @@ def main() -> int:
     log("generating complex64 n=2^24 (seed %d)" % workloads.SEEDS["c2"])
     host = workloads.complex64_normal(k, workloads.SEEDS["c2"])
     x = torch.from_numpy(host).cuda()
-    plan = br.bitrev_plan_query(k, s)
+    cfg = dict(tile_bits=args.tile_bits, variant=args.variant, order=args.order)
+    plan = br.bitrev_plan_query(k, s, **cfg)
     timer = Timer(torch, flush=not args.hot)
 
     def step():
-        br.bitrev_inplace(x, k)
+        br.bitrev_inplace(x, k, **cfg)
 
     log("headline: %d warmup + %d timed in-place steps, plan %s" % (args.warmup, args.steps, plan))
     torch.cuda.synchronize()
@@ -220,6 +241,12 @@ def main() -> int:
     want = host if applied % 2 == 0 else oracle.outofplace(host)
     bit_exact = bool(np.array_equal(got.view(np.uint8), want.view(np.uint8)))
     log("headline %.1f GB/s (mean %.4f ms), bit_exact=%s" % (value, mean_ms, bit_exact))
+
+    # the reference copy of the same bytes under the same flush policy
+    y = torch.empty_like(x)
+    copy_ms = statistics.fmean(timer.time(lambda: br.bitrev_copy(x, y), args.steps))
+    copy_gbs = gbs(nbytes, copy_ms)
+    log("copy %.1f GB/s (mean %.4f ms)" % (copy_gbs, copy_ms))
 
     traffic = read_traffic(nbytes)
     out = {
@@ -239,8 +266,11 @@ def main() -> int:
                                "caches flushed between steps" if not args.hot else
                                "in-place bitrev, complex64, n=2^24 (128 MiB), hot caches",
                    "log2n": k, "elem_size": s, "tile_bits": plan["tile_bits"],
-                   "grid_blocks": plan["grid_blocks"], "block_threads": plan["block_threads"]},
+                   "grid_blocks": plan["grid_blocks"], "block_threads": plan["block_threads"],
+                   "variant": plan["variant"], "order": plan["order"]},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "copy_GBps": round(copy_gbs, 2),
+        "pct_of_copy": round(100.0 * value / copy_gbs, 2),
         "bit_exact": bit_exact,
         "wall_s_timed_loop": round(wall, 4),
         "step_ms_min_median_max": [round(min(times), 5), round(statistics.median(times), 5),
@@ -252,20 +282,16 @@ def main() -> int:
             "unit": "GB/s",
             "frac": round(value / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic, 1),
-            "kernel": "k_tile_inplace<8,%d,vec>" % plan["tile_bits"],
+            "kernel": "%s<8,%d,true>" % ("k_tile_inplace_pipe" if plan["variant"] == 2
+                                         else "k_tile_inplace", plan["tile_bits"]),
             "algorithmic_bytes_per_launch": nbytes,
         },
     }
 
     if not args.no_extras:
         extras = {}
-        y = torch.empty_like(x)
-        c = timer.time(lambda: br.bitrev_copy(x, y), args.steps)
-        extras["copy_GBps"] = round(gbs(nbytes, statistics.fmean(c)), 2)
         c2 = timer.time(lambda: y.copy_(x), args.steps)
         extras["torch_copy_GBps"] = round(gbs(nbytes, statistics.fmean(c2)), 2)
-        best_copy = max(extras["copy_GBps"], extras["torch_copy_GBps"])
-        extras["pct_of_copy"] = round(100.0 * value / best_copy, 2)
         o = timer.time(lambda: br.bitrev_outofplace(x, y), args.steps)
         extras["outofplace_GBps"] = round(gbs(nbytes, statistics.fmean(o)), 2)
         sweep = {}
@@ -280,7 +306,6 @@ def main() -> int:
         extras["tile_sweep"] = sweep
         hot = Timer(torch, flush=False).time(step, args.steps)
         extras["hot_cache_inplace_GBps"] = round(gbs(nbytes, statistics.fmean(hot)), 2)
-        del y
         log("extras: %s" % json.dumps(extras))
         try:
             extras["batched"] = batched_speedup(torch, br, reps=5)

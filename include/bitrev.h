@@ -67,7 +67,11 @@ typedef struct bitrev_config {
                     * work items with a grid stride (persistent); 0 = choose */
   int order;       /* work-item order: 0 = choose, 1 = natural, 2 = balanced
                     * bit dealing (spreads tile rows over HBM channels) */
-  int reserved;    /* must be 0 */
+  int variant;     /* tile kernel: 0 = choose, 1 = one work item per
+                    * workgroup, 2 = persistent and software-pipelined (each
+                    * workgroup loads its next tiles while storing the
+                    * current ones; grid = resident workgroups unless
+                    * grid_blocks is set) */
 } bitrev_config_t;
 
 /* Which code path and geometry a call uses (bitrev_plan_query). */
@@ -86,7 +90,7 @@ typedef struct bitrev_plan {
   int grid_blocks;      /* workgroups launched */
   int order;            /* 1 natural, 2 balanced */
   int vector_access;    /* 1: 16-byte global accesses; 0: one element per access */
-  int reserved;
+  int variant;          /* 1 one item per workgroup, 2 persistent pipelined */
   uint64_t work_items;  /* tile pairs (in place) or tiles (out of place), all rows */
   uint64_t lds_bytes;   /* LDS per workgroup */
 } bitrev_plan_t;

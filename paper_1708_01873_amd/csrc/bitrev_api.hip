@@ -40,8 +40,9 @@ DeviceInfo g_dev[kMaxDevices];
 
 // The current device's properties; MI355X figures when `allow_default` and
 // no device is present (plan queries on a host without a GPU).
-bitrev_status_t device_info(DeviceInfo* out, bool allow_default) {
+bitrev_status_t device_info(DeviceInfo* out, bool allow_default, bool* present = nullptr) {
   int dev = 0;
+  if (present) *present = false;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
     if (allow_default) {
@@ -72,6 +73,7 @@ bitrev_status_t device_info(DeviceInfo* out, bool allow_default) {
     g_dev_known[dev] = true;
   }
   *out = g_dev[dev];
+  if (present) *present = true;
   return BITREV_SUCCESS;
 }
 
@@ -83,6 +85,7 @@ struct TuneEntry {
   int tile_bits = 0;
   int wg_per_cu = 0;
   int order = 0;
+  int variant = 0;
 };
 
 std::mutex g_tune_mu;
@@ -91,8 +94,9 @@ std::once_flag g_tune_env_once;
 
 const char kTuningFormat[] =
     "libbitrev tuning v1: one entry per line, '#' starts a comment; fields: mode "
-    "(inplace|outofplace|batched) elem_size log2n(-1 = any) tile_bits wg_per_cu(0 = default) "
-    "order(0 = default, 1 natural, 2 balanced)";
+    "(inplace|outofplace|batched) elem_size log2n(-1 = any) tile_bits(0 = default) "
+    "wg_per_cu(0 = default) order(0 = default, 1 natural, 2 balanced) "
+    "variant(0 = default, 1 one item per workgroup, 2 persistent pipelined)";
 
 int mode_from_name(const char* s) {
   if (strcmp(s, "inplace") == 0) return 0;
@@ -118,13 +122,15 @@ bitrev_status_t load_tuning_file(const char* path) {
     char* hash = strchr(line, '#');
     if (hash) *hash = '\0';
     char mode[32];
-    int s, k, b, wg, order;
+    int s, k, b, wg, order, variant;
     char extra[8];
-    const int got = sscanf(line, "%31s %d %d %d %d %d %7s", mode, &s, &k, &b, &wg, &order, extra);
+    const int got =
+        sscanf(line, "%31s %d %d %d %d %d %d %7s", mode, &s, &k, &b, &wg, &order, &variant, extra);
     if (got <= 0) continue;  // blank or comment-only line
-    const int md = got >= 6 ? mode_from_name(mode) : -1;
-    if (got != 6 || md < 0 || !valid_elem_size((size_t)s) || k < -1 || k > BITREV_MAX_LOG2N ||
-        b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 || order > 2) {
+    const int md = got >= 7 ? mode_from_name(mode) : -1;
+    if (got != 7 || md < 0 || !valid_elem_size((size_t)s) || k < -1 || k > BITREV_MAX_LOG2N ||
+        b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 || order > 2 ||
+        variant < 0 || variant > 2) {
       ok = false;
       break;
     }
@@ -132,6 +138,7 @@ bitrev_status_t load_tuning_file(const char* path) {
     t.tile_bits = b;
     t.wg_per_cu = wg;
     t.order = order;
+    t.variant = variant;
     table[std::make_tuple(md, s, k)] = t;
   }
   fclose(f);
@@ -161,19 +168,51 @@ TuneEntry tune_lookup(int mode, int s, int k) {
 // ---------------------------------------------------------------------------
 enum { kModeInplace = 0, kModeOutofplace = 1, kModeBatched = 2 };
 
-// Built-in tile width per element size: rows of 2^b * s >= 256 bytes keep
-// every HBM access a run of whole 128-byte lines.
-int default_tile_bits(int s) {
-  switch (s) {
-    case 1: return 7;
-    case 2: return 7;
-    case 4: return 6;
-    case 8: return 5;
-    default: return 4;
+// Built-in plan per (mode, element size, array bytes), from sweeps of every
+// compiled tile width, both work orders and both kernel variants on MI355X
+// (read-flushed caches, arrays of 64 MiB to 4 GiB).  Rows of 2^b * s >= 128
+// bytes keep every HBM access a run of whole 128-byte lines.  Arrays that
+// fit the 256 MiB Infinity Cache twice over favour the persistent pipelined
+// in-place kernel; larger ones the one-item-per-workgroup kernel.
+struct DefaultPlan {
+  int b;
+  int variant;
+  int order;
+};
+
+DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
+  const bool small = array_bytes <= (512ull << 20);
+  if (mode == 0) {  // in place
+    switch (s) {
+      case 1: return {7, small ? 2 : 1, 2};
+      case 2: return {7, small ? 2 : 1, 2};
+      case 4: return {6, small ? 2 : 1, 2};
+      case 8: return small ? DefaultPlan{6, 2, 1} : DefaultPlan{6, 1, 2};
+      default: return small ? DefaultPlan{4, 2, 2} : DefaultPlan{4, 1, 1};
+    }
+  }
+  switch (s) {  // out of place (and batched tile width)
+    case 1: return {7, 1, 2};
+    case 2: return {7, 1, 2};
+    case 4: return {6, 1, 2};
+    case 8: return {5, 1, 2};
+    default: return {4, 1, 2};
   }
 }
 
+int default_tile_bits(int s) { return default_plan(1, s, 0).b; }
+
 int default_order() { return 2; }
+
+int occupancy_of(int s, int b, bool vec, bool inplace, bool pipelined) {
+  switch (s) {
+    case 1: return tile_occupancy_s1(b, vec, inplace, pipelined);
+    case 2: return tile_occupancy_s2(b, vec, inplace, pipelined);
+    case 4: return tile_occupancy_s4(b, vec, inplace, pipelined);
+    case 8: return tile_occupancy_s8(b, vec, inplace, pipelined);
+    default: return tile_occupancy_s16(b, vec, inplace, pipelined);
+  }
+}
 
 int threads_of(int s, int b, bool vec) {
   switch (s) {
@@ -188,7 +227,7 @@ int threads_of(int s, int b, bool vec) {
 bool valid_config(const bitrev_config_t* c) {
   if (!c) return true;
   return c->tile_bits >= 0 && c->tile_bits <= kMaxTileBits && c->grid_blocks >= 0 &&
-         c->order >= 0 && c->order <= 2 && c->reserved == 0;
+         c->order >= 0 && c->order <= 2 && c->variant >= 0 && c->variant <= 2;
 }
 
 uint32_t round_up(uint64_t v, uint32_t to) {
@@ -203,6 +242,8 @@ uint32_t default_grid(uint64_t items, const DeviceInfo& d) {
   return round_up(items < cap ? items : cap, (uint32_t)d.xcds);
 }
 
+int resident_per_cu(int threads, size_t lds);
+
 struct Plan {
   int path = BITREV_PATH_NONE;
   int b = 0;
@@ -210,6 +251,7 @@ struct Plan {
   int threads = 0;
   uint32_t grid = 0;
   int order = 2;
+  int variant = 1;
   bool vec = true;
   uint64_t items_per_seg = 0;
   uint64_t total = 0;
@@ -219,12 +261,13 @@ struct Plan {
 // Plan for a plain call (mode 0 or 1) on `rows` arrays of 2^k elements.
 // align: the largest power of two (<= 16) dividing both data pointers.
 bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_config_t* cfg,
-                           size_t align, const DeviceInfo& d, Plan* p) {
+                           size_t align, const DeviceInfo& d, bool have_device, Plan* p) {
   *p = Plan();
   if (rows == 0 || (mode == kModeInplace && k <= 1)) return BITREV_SUCCESS;
   const int forced_b = cfg ? cfg->tile_bits : 0;
   const TuneEntry te = tune_lookup(mode, s, k);
-  p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : default_order());
+  const DefaultPlan dp = default_plan(mode, s, ((uint64_t)s) << k);
+  p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : dp.order);
   if (forced_b == 0 && k <= 6) {
     p->path = BITREV_PATH_WAVE;
     p->threads = 256;
@@ -242,7 +285,7 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
         tile_lds_bytes_for(s, b, inplace_tiles) > d.lds_per_block)
       return BITREV_ERROR_NOT_SUPPORTED;
   } else {
-    b = te.tile_bits ? te.tile_bits : default_tile_bits(s);
+    b = te.tile_bits ? te.tile_bits : dp.b;
     if (b > max_tile_bits(s)) b = max_tile_bits(s);
     if (2 * b > k) b = k / 2;
     while (b > 0 && tile_lds_bytes_for(s, b, inplace_tiles) > d.lds_per_block) --b;
@@ -259,10 +302,17 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
   p->total = p->items_per_seg * (uint64_t)rows;
   p->threads = threads_of(s, b, p->vec);
   p->lds = tile_lds_bytes_for(s, b, inplace_tiles);
+  p->variant = (cfg && cfg->variant) ? cfg->variant : (te.variant ? te.variant : dp.variant);
   if (cfg && cfg->grid_blocks > 0) {
     p->grid = round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds);
   } else if (te.wg_per_cu > 0) {
     p->grid = round_up((uint64_t)te.wg_per_cu * d.cus, (uint32_t)d.xcds);
+  } else if (p->variant == 2) {
+    // persistent: the workgroups that are resident at once
+    int occ = have_device ? occupancy_of(s, b, p->vec, mode == kModeInplace, true) : 0;
+    if (occ <= 0) occ = resident_per_cu(p->threads, p->lds);
+    const uint64_t g = (uint64_t)occ * d.cus;
+    p->grid = round_up(g < p->total ? g : p->total, (uint32_t)d.xcds);
   } else {
     p->grid = default_grid(p->total, d);
   }
@@ -281,7 +331,8 @@ int resident_per_cu(int threads, size_t lds) {
 bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo& d, Plan* p) {
   *p = Plan();
   const TuneEntry te = tune_lookup(kModeBatched, s, -1);
-  int b = (cfg && cfg->tile_bits) ? cfg->tile_bits : (te.tile_bits ? te.tile_bits : default_tile_bits(s));
+  int b = (cfg && cfg->tile_bits) ? cfg->tile_bits
+                                   : (te.tile_bits ? te.tile_bits : default_tile_bits(s));
   if (!(cfg && cfg->tile_bits) && b > max_tile_bits(s)) b = max_tile_bits(s);
   if (b < kMinBatchedTileBits || b > max_tile_bits(s) ||
       tile_lds_bytes_for(s, b, 2) > d.lds_per_block)
@@ -315,6 +366,7 @@ hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void
   a.balanced = p.order == 2 ? 1 : 0;
   a.xcds = d.xcds;
   a.grid = p.grid;
+  a.pipelined = p.variant == 2 ? 1 : 0;
   switch (s) {
     case 1: return inplace ? launch_tile_inplace_s1(p.b, p.vec, a, st) : launch_tile_outofplace_s1(p.b, p.vec, a, st);
     case 2: return inplace ? launch_tile_inplace_s2(p.b, p.vec, a, st) : launch_tile_outofplace_s2(p.b, p.vec, a, st);
@@ -375,7 +427,7 @@ bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_
   if (st != BITREV_SUCCESS) return st;
   Plan p;
   st = plan_plain(inplace ? kModeInplace : kModeOutofplace, k, (int)s, rows, cfg,
-                  pointer_align(src, dst), d, &p);
+                  pointer_align(src, dst), d, true, &p);
   if (st != BITREV_SUCCESS) return st;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
@@ -501,11 +553,12 @@ bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int
       rows < 0 || (mode != 2 && (log2n < 0 || log2n > BITREV_MAX_LOG2N)))
     return BITREV_ERROR_INVALID_VALUE;
   DeviceInfo d;
-  bitrev_status_t st = device_info(&d, true);
+  bool have_device = false;
+  bitrev_status_t st = device_info(&d, true, &have_device);
   if (st != BITREV_SUCCESS) return st;
   Plan p;
   st = (mode == 2) ? plan_batched((int)elem_size, cfg, d, &p)
-                   : plan_plain(mode, log2n, (int)elem_size, rows, cfg, 16, d, &p);
+                   : plan_plain(mode, log2n, (int)elem_size, rows, cfg, 16, d, have_device, &p);
   if (st != BITREV_SUCCESS) return st;
   memset(plan, 0, sizeof *plan);
   plan->path = p.path;
@@ -515,6 +568,7 @@ bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int
   plan->grid_blocks = (int)p.grid;
   plan->order = p.order;
   plan->vector_access = p.vec ? 1 : 0;
+  plan->variant = p.path == BITREV_PATH_TILE ? p.variant : 0;
   plan->work_items = p.total;
   plan->lds_bytes = p.lds;
   return BITREV_SUCCESS;
@@ -534,7 +588,7 @@ bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stre
   DeviceInfo d;
   bitrev_status_t st = device_info(&d, false);
   if (st != BITREV_SUCCESS) return st;
-  const hipError_t e = launch_copy(src, dst, bytes, (uint32_t)(d.cus * 16),
+  const hipError_t e = launch_copy(src, dst, bytes, (uint32_t)(d.cus * 4),
                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
 }

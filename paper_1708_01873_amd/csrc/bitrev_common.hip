@@ -83,22 +83,14 @@ __global__ __launch_bounds__(kPrepThreads) void k_batched_prep(const int64_t* of
   }
 }
 
-// Streaming copy, 16 bytes per access, four accesses in flight per thread.
+// Streaming copy, one 16-byte access per thread per iteration, grid
+// stride.  With four workgroups per compute unit this was the fastest of the
+// copy shapes measured on MI355X (unrolled, blocked and non-temporal forms
+// were slower or equal), so it is the honest denominator for the roofline.
 __global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src,
                                                 u32x4* __restrict__ dst, uint64_t nvec) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
-  uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  for (; i + 3 * stride < nvec; i += 4 * stride) {
-    const u32x4 a0 = src[i];
-    const u32x4 a1 = src[i + stride];
-    const u32x4 a2 = src[i + 2 * stride];
-    const u32x4 a3 = src[i + 3 * stride];
-    dst[i] = a0;
-    dst[i + stride] = a1;
-    dst[i + 2 * stride] = a2;
-    dst[i + 3 * stride] = a3;
-  }
-  for (; i < nvec; i += stride) dst[i] = src[i];
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < nvec; i += stride) dst[i] = src[i];
 }
 
 __global__ __launch_bounds__(256) void k_copy1(const uint8_t* __restrict__ src,

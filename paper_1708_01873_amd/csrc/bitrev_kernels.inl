@@ -52,6 +52,108 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
   }
 }
 
+// Where work item `item` lives: its array's base and its middle bits.
+template <typename E>
+__device__ __forceinline__ E* item_base(void* data, uint64_t item, uint64_t items_per_seg,
+                                        uint64_t total_items, uint64_t seg_elems, uint64_t* local) {
+  uint64_t seg = 0;
+  *local = item;
+  if (items_per_seg != total_items) {
+    seg = item / items_per_seg;
+    *local = item - seg * items_per_seg;
+  }
+  return static_cast<E*>(data) + seg * seg_elems;
+}
+
+// In place, persistent and software-pipelined: each workgroup walks its work
+// items with a grid stride and issues the global loads of the next tile pair
+// before it writes out the current one, so that every workgroup keeps reads
+// and writes in flight together.  The register copy of the next pair is
+// taken only after the current pair sits in LDS.
+template <int S, int B, bool VEC>
+__global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace_pipe(
+    void* data, int m, uint64_t items_per_seg, uint64_t total_items, uint64_t seg_elems,
+    int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  typedef TileShape<S, B, VEC> Sh;
+  constexpr int NT = tile_threads<S, B, VEC>();
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  __shared__ E lds[2 * Sh::TILE_E];
+  const uint64_t rowstride = 1ull << (m + B);
+  Chunk<S, Sh::VB> ra[PT], rb[PT];
+  uint64_t item = xcd_block(xcds);
+  if (item >= total_items) return;
+  uint64_t local;
+  E* base = item_base<E>(data, item, items_per_seg, total_items, seg_elems, &local);
+  uint32_t y = pair_at(m, local, balanced != 0);
+  uint32_t yr = rev_bits(y, m);
+  tile_load<S, B, VEC, NT, PT>(ra, base, rowstride, y);
+  if (yr != y) tile_load<S, B, VEC, NT, PT>(rb, base, rowstride, yr);
+  while (true) {
+    tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+    if (yr != y) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+    __syncthreads();
+    const uint64_t next = item + gridDim.x;
+    E* nbase = base;
+    uint32_t ny = 0, nyr = 0;
+    if (next < total_items) {
+      nbase = item_base<E>(data, next, items_per_seg, total_items, seg_elems, &local);
+      ny = pair_at(m, local, balanced != 0);
+      nyr = rev_bits(ny, m);
+      tile_load<S, B, VEC, NT, PT>(ra, nbase, rowstride, ny);
+      if (nyr != ny) tile_load<S, B, VEC, NT, PT>(rb, nbase, rowstride, nyr);
+    }
+    tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
+    if (yr != y) tile_store<S, B, VEC, NT, PT>(base, rowstride, y, lds + Sh::TILE_E);
+    if (next >= total_items) break;
+    __syncthreads();
+    item = next;
+    base = nbase;
+    y = ny;
+    yr = nyr;
+  }
+}
+
+// Out of place, persistent and software-pipelined (see k_tile_inplace_pipe).
+template <int S, int B, bool VEC>
+__global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace_pipe(
+    const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
+    uint64_t seg_elems, int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  typedef TileShape<S, B, VEC> Sh;
+  constexpr int NT = tile_threads<S, B, VEC>();
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  __shared__ E lds[Sh::TILE_E];
+  const uint64_t rowstride = 1ull << (m + B);
+  Chunk<S, Sh::VB> ra[PT];
+  uint64_t item = xcd_block(xcds);
+  if (item >= total_items) return;
+  uint64_t local;
+  const E* in = item_base<E>(const_cast<void*>(src), item, items_per_seg, total_items, seg_elems, &local);
+  E* out = static_cast<E*>(dst) + (in - static_cast<const E*>(src));
+  uint32_t y = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
+  tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
+  while (true) {
+    tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+    __syncthreads();
+    const uint64_t next = item + gridDim.x;
+    const E* nin = in;
+    uint32_t ny = 0;
+    if (next < total_items) {
+      nin = item_base<E>(const_cast<void*>(src), next, items_per_seg, total_items, seg_elems, &local);
+      ny = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
+      tile_load<S, B, VEC, NT, PT>(ra, nin, rowstride, ny);
+    }
+    tile_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
+    if (next >= total_items) break;
+    __syncthreads();
+    item = next;
+    in = nin;
+    out = static_cast<E*>(dst) + (in - static_cast<const E*>(src));
+    y = ny;
+  }
+}
+
 // n = 2^k <= 64: one wavefront per array, four arrays per workgroup.
 template <int S>
 __global__ __launch_bounds__(256) void k_wave(const void* src, void* dst, int k, uint64_t nseg) {
@@ -116,18 +218,46 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched(
 
 template <int S, int B, bool VEC>
 hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_tile_inplace<S, B, VEC>), dim3(a.grid), dim3(tile_threads<S, B, VEC>()),
-                     0, st, a.dst, a.m, a.items_per_seg, a.total_items, a.seg_elems, a.balanced,
-                     a.xcds);
+  if (a.pipelined) {
+    hipLaunchKernelGGL((k_tile_inplace_pipe<S, B, VEC>), dim3(a.grid),
+                       dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
+                       a.total_items, a.seg_elems, a.balanced, a.xcds);
+  } else {
+    hipLaunchKernelGGL((k_tile_inplace<S, B, VEC>), dim3(a.grid), dim3(tile_threads<S, B, VEC>()),
+                       0, st, a.dst, a.m, a.items_per_seg, a.total_items, a.seg_elems, a.balanced,
+                       a.xcds);
+  }
   return hipGetLastError();
 }
 
 template <int S, int B, bool VEC>
 hipError_t run_tile_outofplace(const TileLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC>), dim3(a.grid),
-                     dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
-                     a.total_items, a.seg_elems, a.balanced, a.xcds);
+  if (a.pipelined) {
+    hipLaunchKernelGGL((k_tile_outofplace_pipe<S, B, VEC>), dim3(a.grid),
+                       dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
+                       a.total_items, a.seg_elems, a.balanced, a.xcds);
+  } else {
+    hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC>), dim3(a.grid),
+                       dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
+                       a.total_items, a.seg_elems, a.balanced, a.xcds);
+  }
   return hipGetLastError();
+}
+
+// Workgroups of a tile kernel that fit on one compute unit at once.
+template <int S, int B, bool VEC>
+int occupancy_of(bool inplace, bool pipelined) {
+  int n = 0;
+  hipError_t e;
+  const int nt = tile_threads<S, B, VEC>();
+  if (inplace) {
+    e = pipelined ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_inplace_pipe<S, B, VEC>, nt, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_inplace<S, B, VEC>, nt, 0);
+  } else {
+    e = pipelined ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_outofplace_pipe<S, B, VEC>, nt, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_outofplace<S, B, VEC>, nt, 0);
+  }
+  return e == hipSuccess ? n : 0;
 }
 
 template <int S, int B>
@@ -158,6 +288,16 @@ hipError_t dispatch_batched(const BatchedLaunch& a, hipStream_t st) {
   } else {
     if (a.b == B) return run_batched<S, B>(a, st);
     return dispatch_batched<S, B + 1>(a, st);
+  }
+}
+
+template <int S, int B = 0>
+int occupancy_for(int b, bool vec, bool inplace, bool pipelined) {
+  if constexpr (B > max_tile_bits(S)) {
+    return 0;
+  } else {
+    if (b == B) return vec ? occupancy_of<S, B, true>(inplace, pipelined) : occupancy_of<S, B, false>(inplace, pipelined);
+    return occupancy_for<S, B + 1>(b, vec, inplace, pipelined);
   }
 }
 
@@ -196,6 +336,10 @@ hipError_t BITREV_CAT(launch_batched_s, BITREV_S)(const BatchedLaunch& a, hipStr
 }
 
 int BITREV_CAT(tile_threads_s, BITREV_S)(int b, bool vec) { return threads_for<BITREV_S>(b, vec); }
+
+int BITREV_CAT(tile_occupancy_s, BITREV_S)(int b, bool vec, bool inplace, bool pipelined) {
+  return occupancy_for<BITREV_S>(b, vec, inplace, pipelined);
+}
 
 int BITREV_CAT(batched_threads_s, BITREV_S)(int b) {
   return b < kMinBatchedTileBits ? 0 : threads_for<BITREV_S>(b, true);

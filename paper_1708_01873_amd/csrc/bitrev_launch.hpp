@@ -26,6 +26,7 @@ struct TileLaunch {
   int balanced;             // work-item order: 0 natural, 1 balanced bit dealing
   int xcds;                 // number of XCDs the grid is dealt over
   uint32_t grid;            // workgroups (multiple of xcds)
+  int pipelined;            // 1: persistent software-pipelined kernel
 };
 
 struct WaveLaunch {
@@ -64,6 +65,7 @@ size_t tile_lds_bytes(int s, int b, bool inplace);
   hipError_t launch_wave_s##S(const WaveLaunch& a, hipStream_t st);                  \
   hipError_t launch_batched_s##S(const BatchedLaunch& a, hipStream_t st);            \
   int tile_threads_s##S(int b, bool vec);                                            \
+  int tile_occupancy_s##S(int b, bool vec, bool inplace, bool pipelined);            \
   int batched_threads_s##S(int b);
 
 BITREV_DECLARE_LAUNCHERS(1)

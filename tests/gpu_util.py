@@ -30,7 +30,7 @@ def to_device(host_bytes: np.ndarray, s: int, pad_front: int = 0):
 def to_host_bytes(t) -> np.ndarray:
     import torch
     torch.cuda.synchronize()
-    return t.contiguous().cpu().numpy().view(np.uint8).reshape(-1)
+    return t.detach().contiguous().cpu().numpy().view(np.uint8).reshape(-1)
 
 
 def assert_bytes_equal(got: np.ndarray, want: np.ndarray, what: str = "") -> None:

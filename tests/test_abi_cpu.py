@@ -89,7 +89,7 @@ def test_rows_validation(L):
 
 def test_config_validation(L):
     for cfg in (br.Config(8, 0, 0, 0), br.Config(-1, 0, 0, 0), br.Config(0, -5, 0, 0),
-                br.Config(0, 0, 3, 0), br.Config(0, 0, 0, 1)):
+                br.Config(0, 0, 3, 0), br.Config(0, 0, 0, 3), br.Config(0, 0, 0, -1)):
         assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
 
 
@@ -125,11 +125,18 @@ def test_copy_validation(L):
 
 
 def test_plan_query_defaults(L):
-    p = br.bitrev_plan_query(24, 8)
+    p = br.bitrev_plan_query(24, 8, tile_bits=5, variant=br.VARIANT_ONE_ITEM)
     assert p["path"] == br.PATH_TILE and p["tile_bits"] == 5 and p["mid_bits"] == 14
     assert p["work_items"] == (2**14 + 2**7) // 2
-    assert p["grid_blocks"] % 8 == 0
+    assert p["grid_blocks"] % 8 == 0 and p["grid_blocks"] >= p["work_items"]
+    # built-in plans measured on MI355X: complex64 2^24 in place -> b = 6,
+    # persistent pipelined; a 2 GiB array -> one item per workgroup
+    p = br.bitrev_plan_query(24, 8)
+    assert (p["tile_bits"], p["variant"], p["order"]) == (6, 2, 1)
+    p = br.bitrev_plan_query(28, 8)
+    assert (p["tile_bits"], p["variant"], p["order"]) == (6, 1, 2)
     p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
+    assert (p["tile_bits"], p["variant"], p["order"]) == (5, 1, 2)
     assert p["work_items"] == 2**14
     p = br.bitrev_plan_query(5, 4)
     assert p["path"] == br.PATH_WAVE
@@ -148,31 +155,38 @@ def test_plan_query_defaults(L):
         br.bitrev_plan_query(8, 8, tile_bits=5)  # 2b > k
     p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
     assert p["path"] == br.PATH_BATCHED and p["grid_blocks"] % 8 == 0
+    # the persistent pipelined variant launches at most the resident workgroups
+    p = br.bitrev_plan_query(24, 8, variant=br.VARIANT_PIPELINED)
+    assert p["variant"] == br.VARIANT_PIPELINED and p["grid_blocks"] % 8 == 0
+    assert 256 <= p["grid_blocks"] <= min(p["work_items"] + 7, 256 * 32)
+    p = br.bitrev_plan_query(24, 8, variant=br.VARIANT_ONE_ITEM)
+    assert p["variant"] == br.VARIANT_ONE_ITEM and p["grid_blocks"] >= p["work_items"]
 
 
 def test_tuning_file(L, tmp_path):
     good = tmp_path / "tune.txt"
-    good.write_text("# comment\n\ninplace 8 24 6 0 2   # trailing comment\n"
-                    "batched 8 -1 4 4 1\n")
+    good.write_text("# comment\n\ninplace 8 24 5 0 2 1   # trailing comment\n"
+                    "batched 8 -1 4 4 1 0\n")
     br.bitrev_load_tuning(str(good))
     try:
-        assert br.bitrev_plan_query(24, 8)["tile_bits"] == 6
-        assert br.bitrev_plan_query(22, 8)["tile_bits"] == 5  # no entry: default
+        p = br.bitrev_plan_query(24, 8)
+        assert (p["tile_bits"], p["order"], p["variant"]) == (5, 2, 1)
+        assert br.bitrev_plan_query(22, 8)["tile_bits"] == 6  # no entry: default
         p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
         assert p["tile_bits"] == 4 and p["order"] == 1 and p["grid_blocks"] == 4 * 256
-        for bad in ("inplace 8 24 6 0\n", "sideways 8 24 6 0 2\n", "inplace 3 24 6 0 2\n",
-                    "inplace 8 24 9 0 2\n", "inplace 8 24 6 0 2 7\n"):
+        for bad in ("inplace 8 24 6 0 2\n", "sideways 8 24 6 0 2 0\n", "inplace 3 24 6 0 2 0\n",
+                    "inplace 8 24 9 0 2 0\n", "inplace 8 24 6 0 2 3\n", "inplace 8 24 6 0 2 0 7\n"):
             f = tmp_path / "bad.txt"
             f.write_text(bad)
             with pytest.raises(br.BitrevError):
                 br.bitrev_load_tuning(str(f))
             # a rejected file leaves the loaded table in place
-            assert br.bitrev_plan_query(24, 8)["tile_bits"] == 6
+            assert br.bitrev_plan_query(24, 8)["tile_bits"] == 5
         with pytest.raises(br.BitrevError):
             br.bitrev_load_tuning(str(tmp_path / "missing.txt"))
     finally:
         br.bitrev_load_tuning(None)
-    assert br.bitrev_plan_query(24, 8)["tile_bits"] == 5
+    assert br.bitrev_plan_query(24, 8)["tile_bits"] == 6
     assert "tuning" in br.bitrev_tuning_format()
 
 

@@ -76,10 +76,12 @@ def test_forced_tile_widths(s):
             host = workloads.byte_pattern((1 << k) * s, seed=7 * k + b)
             want = oracle.outofplace(host, s)
             for order in (1, 2):
-                for inplace in (True, False):
-                    got = _run(host, k, s, inplace, tile_bits=b, order=order)
-                    assert_bytes_equal(got, want, "s=%d b=%d k=%d order=%d ip=%s"
-                                       % (s, b, k, order, inplace))
+                for variant in (1, 2):
+                    for inplace in (True, False):
+                        got = _run(host, k, s, inplace, tile_bits=b, order=order,
+                                   variant=variant)
+                        assert_bytes_equal(got, want, "s=%d b=%d k=%d order=%d variant=%d ip=%s"
+                                           % (s, b, k, order, variant, inplace))
 
 
 @pytest.mark.parametrize("s", (1, 2, 4, 8))
@@ -102,8 +104,24 @@ def test_persistent_grid(grid):
     want = oracle.outofplace(host, s)
     for inplace in (True, False):
         for order in (1, 2):
-            got = _run(host, k, s, inplace, grid_blocks=grid, order=order)
-            assert_bytes_equal(got, want, "grid=%d ip=%s order=%d" % (grid, inplace, order))
+            for variant in (1, 2):
+                got = _run(host, k, s, inplace, grid_blocks=grid, order=order, variant=variant)
+                assert_bytes_equal(got, want, "grid=%d ip=%s order=%d variant=%d"
+                                   % (grid, inplace, order, variant))
+
+
+@pytest.mark.parametrize("s", (4, 8, 16))
+def test_pipelined_rows(s):
+    """The persistent pipelined kernels walk items across row boundaries."""
+    for k, rows in ((12, 33), (14, 5)):
+        host = workloads.byte_pattern((rows << k) * s, seed=k + rows + s)
+        want = oracle.rows(host, k, s)
+        x = to_device(host, s)
+        y = torch.empty_like(x)
+        br.bitrev_rows(x, y, k, variant=2)
+        assert_bytes_equal(to_host_bytes(y), want, "rows oop pipelined s=%d k=%d" % (s, k))
+        br.bitrev_rows(x, x, k, variant=2, grid_blocks=16)
+        assert_bytes_equal(to_host_bytes(x), want, "rows ip pipelined s=%d k=%d" % (s, k))
 
 
 def test_guard_regions_untouched():
