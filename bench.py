@@ -304,6 +304,14 @@ def main() -> int:
                     "inplace_GBps": round(gbs(nbytes, statistics.fmean(ti)), 2),
                     "outofplace_GBps": round(gbs(nbytes, statistics.fmean(to)), 2)}
         extras["tile_sweep"] = sweep
+        rec = timer.time(lambda: br.bitrev_inplace_recursive(x, k), args.steps)
+        rec_ms = statistics.fmean(rec)
+        extras["paper_recursive_scheme"] = {
+            "what": "the paper's recursive method, one recursion level: block-local reversals, "
+                    "in-place square transpose, block-local reversals (3 passes)",
+            "GBps_effective": round(gbs(nbytes, rec_ms), 2),
+            "ms": round(rec_ms, 5),
+            "slowdown_vs_one_pass": round(rec_ms / mean_ms, 3)}
         hot = Timer(torch, flush=False).time(step, args.steps)
         extras["hot_cache_inplace_GBps"] = round(gbs(nbytes, statistics.fmean(hot)), 2)
         log("extras: %s" % json.dumps(extras))

@@ -191,6 +191,26 @@ bitrev_status_t bitrev_load_tuning(const char* path);
 const char* bitrev_tuning_format(void);
 
 /* ------------------------------------------------------------------------ */
+/* The paper's recursive scheme, as an A/B baseline for the one-pass kernels */
+/* ------------------------------------------------------------------------ */
+
+/* In place, by the paper's cache-oblivious recursive method with one level of
+ * recursion (Methods, "cache-oblivious recursive bit-reversed permutation";
+ * Results, where the GPU variant uses this scheme): with k = log2n even and
+ * h = k/2, (1) reverse the low h bits within each of the 2^h contiguous
+ * blocks, (2) transpose the 2^h x 2^h matrix in place, (3) reverse within each
+ * block again.  Three passes over the array (3 * 2 n s bytes) where
+ * bitrev_inplace makes one; the result is identical.  Odd log2n returns
+ * BITREV_ERROR_NOT_SUPPORTED (the paper's odd-k pre-step needs an n/2
+ * buffer).  Arguments as bitrev_inplace. */
+bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size, void* stream);
+
+/* In-place transpose of a square 2^log2side x 2^log2side row-major matrix of
+ * elem_size-byte elements (the middle step above): element (r, c) moves to
+ * (c, r).  2 * log2side <= BITREV_MAX_LOG2N. */
+bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_size, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Reference copy (the HBM roofline denominator), status, version            */
 /* ------------------------------------------------------------------------ */
 
@@ -216,6 +236,8 @@ uint64_t bitrev_debug_pair_count(int m);
 uint32_t bitrev_debug_pair_at(int m, uint64_t w, int balanced);
 /* The balanced bit dealing of a width-bit value. */
 uint32_t bitrev_debug_spread(uint32_t w, int width);
+/* The w-th tile pair (r <= c) of the square transpose, column by column. */
+void bitrev_debug_tri_pair(uint64_t w, uint32_t* r, uint32_t* c);
 
 #ifdef __cplusplus
 }

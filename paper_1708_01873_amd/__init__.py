@@ -80,6 +80,8 @@ _SIGNATURES = {
     "bitrev_load_tuning": ([ctypes.c_char_p], _I),
     "bitrev_tuning_format": ([], ctypes.c_char_p),
     "bitrev_copy": ([_VP, _VP, _SZ, _VP], _I),
+    "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
+    "bitrev_transpose_inplace": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_status_string": ([_I], ctypes.c_char_p),
     "bitrev_last_hip_error": ([], _I),
     "bitrev_abi_version": ([], _I),
@@ -87,6 +89,8 @@ _SIGNATURES = {
     "bitrev_debug_pair_count": ([_I], ctypes.c_uint64),
     "bitrev_debug_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
     "bitrev_debug_spread": ([ctypes.c_uint32, _I], ctypes.c_uint32),
+    "bitrev_debug_tri_pair": ([ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32),
+                               ctypes.POINTER(ctypes.c_uint32)], None),
 }
 EXPORTED = tuple(_SIGNATURES)
 
@@ -285,6 +289,30 @@ def bitrev_copy(src, dst, stream=None):
     return dst
 
 
+def bitrev_inplace_recursive(data, log2n: Optional[int] = None, *, stream=None):
+    """In place by the paper's recursive scheme (three passes: block-local
+    reversals, square transpose, block-local reversals); log2n must be even.
+    An A/B baseline for bitrev_inplace, which makes one pass."""
+    ptr, s = _tensor_args(data, "data")
+    k = _log2_exact(data.numel()) if log2n is None else int(log2n)
+    _check(_load().bitrev_inplace_recursive(ptr, k, s, _stream(stream)),
+           "bitrev_inplace_recursive")
+    return data
+
+
+def bitrev_transpose_inplace(data, log2side: Optional[int] = None, *, stream=None):
+    """Transpose the square 2^log2side x 2^log2side matrix ``data`` in place
+    (default: from a 2-D square tensor's shape)."""
+    ptr, s = _tensor_args(data, "data")
+    if log2side is None:
+        if data.dim() != 2 or data.shape[0] != data.shape[1]:
+            raise ValueError("give log2side or a square 2-D tensor")
+        log2side = _log2_exact(data.shape[0])
+    _check(_load().bitrev_transpose_inplace(ptr, int(log2side), s, _stream(stream)),
+           "bitrev_transpose_inplace")
+    return data
+
+
 def bitrev_plan_query(log2n: int, elem_size: int, rows: int = 1, mode: int = MODE_INPLACE,
                       *, tile_bits=0, grid_blocks=0, order=0, variant=0, config=None) -> dict:
     """The plan a call would use (no launch)."""
@@ -311,4 +339,5 @@ __all__ = [
     "bitrev_inplace", "bitrev_outofplace", "bitrev_rows", "bitrev_batched",
     "bitrev_batched_workspace_size", "bitrev_batched_errors", "bitrev_copy",
     "bitrev_plan_query", "bitrev_load_tuning", "bitrev_tuning_format",
+    "bitrev_inplace_recursive", "bitrev_transpose_inplace",
 ]

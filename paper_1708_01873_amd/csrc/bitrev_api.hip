@@ -439,9 +439,63 @@ bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
 }
 
+hipError_t launch_transpose(int s, int b, bool vec, const TransposeLaunch& a, hipStream_t st) {
+  switch (s) {
+    case 1: return launch_transpose_s1(b, vec, a, st);
+    case 2: return launch_transpose_s2(b, vec, a, st);
+    case 4: return launch_transpose_s4(b, vec, a, st);
+    case 8: return launch_transpose_s8(b, vec, a, st);
+    default: return launch_transpose_s16(b, vec, a, st);
+  }
+}
+
+// In-place transpose of the 2^h x 2^h matrix at data (validated by callers).
+bitrev_status_t run_transpose(void* data, int h, size_t s, hipStream_t st) {
+  if (h == 0) return BITREV_SUCCESS;
+  DeviceInfo d;
+  bitrev_status_t status = device_info(&d, false);
+  if (status != BITREV_SUCCESS) return status;
+  int b = default_plan(0, (int)s, ((uint64_t)s) << (2 * h)).b;
+  if (b > h) b = h;
+  if (b > max_tile_bits((int)s)) b = max_tile_bits((int)s);
+  while (b > 0 && tile_lds_bytes_for((int)s, b, 2) > d.lds_per_block) --b;
+  const size_t vb = (s << b) < 16 ? (s << b) : 16;
+  TransposeLaunch a;
+  a.data = data;
+  a.h = h;
+  const uint64_t nt = 1ull << (h - b);
+  a.total_items = nt * (nt + 1) / 2;
+  a.xcds = d.xcds;
+  a.grid = default_grid(a.total_items, d);
+  const hipError_t e = launch_transpose((int)s, b, pointer_align(data, data) % vb == 0, a, st);
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
 }  // namespace
 
 extern "C" {
+
+bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_size, void* stream) {
+  if (data == NULL || log2side < 0 || 2 * log2side > BITREV_MAX_LOG2N || !valid_elem_size(elem_size) ||
+      reinterpret_cast<uintptr_t>(data) % elem_size)
+    return BITREV_ERROR_INVALID_VALUE;
+  if (log2side > 32) return BITREV_ERROR_NOT_SUPPORTED;
+  return run_transpose(data, log2side, elem_size, static_cast<hipStream_t>(stream));
+}
+
+bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size, void* stream) {
+  if (data == NULL || log2n < 0 || log2n > BITREV_MAX_LOG2N || !valid_elem_size(elem_size) ||
+      reinterpret_cast<uintptr_t>(data) % elem_size)
+    return BITREV_ERROR_INVALID_VALUE;
+  if (log2n % 2) return BITREV_ERROR_NOT_SUPPORTED;
+  if (log2n <= 1) return BITREV_SUCCESS;
+  const int h = log2n / 2;
+  const int64_t rows = (int64_t)1 << h;
+  bitrev_status_t st = run_plain(data, data, h, rows, elem_size, NULL, stream, true);
+  if (st == BITREV_SUCCESS) st = run_transpose(data, h, elem_size, static_cast<hipStream_t>(stream));
+  if (st == BITREV_SUCCESS) st = run_plain(data, data, h, rows, elem_size, NULL, stream, true);
+  return st;
+}
 
 bitrev_status_t bitrev_inplace(void* data, int log2n, size_t elem_size, void* stream) {
   return run_plain(data, data, log2n, 1, elem_size, NULL, stream, false);
@@ -618,6 +672,13 @@ uint64_t bitrev_debug_pair_count(int m) { return (m < 0 || m > 32) ? 0 : pair_co
 uint32_t bitrev_debug_pair_at(int m, uint64_t w, int balanced) {
   if (m < 0 || m > 32 || w >= pair_count(m)) return 0xFFFFFFFFu;
   return pair_at(m, w, balanced != 0);
+}
+
+void bitrev_debug_tri_pair(uint64_t w, uint32_t* r, uint32_t* c) {
+  uint32_t rr = 0, cc = 0;
+  tri_pair(w, &rr, &cc);
+  if (r) *r = rr;
+  if (c) *c = cc;
 }
 
 uint32_t bitrev_debug_spread(uint32_t w, int width) {

@@ -175,8 +175,9 @@ __device__ __forceinline__ void tile_load(Chunk<S, TileShape<S, B, VEC>::VB> (&r
 }
 
 // Scatter registers into LDS in destination order: source (x, z) goes to
-// LDS row rev_b(z), column rev_b(x).
-template <int S, int B, bool VEC, int NT, int PT>
+// LDS row rev_b(z), column rev_b(x) -- or, with REV = false (the plain
+// square transpose), to row z, column x.
+template <int S, int B, bool VEC, int NT, int PT, bool REV = true>
 __device__ __forceinline__ void tile_scatter(const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
                                              typename Bytes<S>::T* lds) {
   typedef TileShape<S, B, VEC> Sh;
@@ -186,10 +187,11 @@ __device__ __forceinline__ void tile_scatter(const Chunk<S, TileShape<S, B, VEC>
     if (Sh::CPT % NT == 0 || q < Sh::CPT) {
       const int x = q / Sh::CPR;
       const int zc = q % Sh::CPR;
-      const uint32_t col = rev_c<B>((uint32_t)x);
+      const uint32_t col = REV ? rev_c<B>((uint32_t)x) : (uint32_t)x;
 #pragma unroll
       for (int j = 0; j < Sh::CE; ++j) {
-        const uint32_t row = rev_c<B>((uint32_t)(zc * Sh::CE + j));
+        const uint32_t z = (uint32_t)(zc * Sh::CE + j);
+        const uint32_t row = REV ? rev_c<B>(z) : z;
         lds[row * Sh::PE + col] = reg[i].e[j];
       }
     }
@@ -252,6 +254,44 @@ __device__ __forceinline__ void tile_outofplace(const typename Bytes<S>::T* __re
   tile_scatter<S, B, VEC, NT, PT>(ra, lds);
   __syncthreads();
   tile_store<S, B, VEC, NT, PT>(dst, rowstride, rev_bits(y, m), lds);
+}
+
+// ---------------------------------------------------------------------------
+// In-place square transpose (the middle step of the paper's recursive
+// method, Methods): a 2^h x 2^h matrix in 2^b x 2^b tiles; tiles (R, C) and
+// (C, R) swap through LDS, each transposed; diagonal tiles transpose alone.
+// ---------------------------------------------------------------------------
+
+// The w-th pair (R, C) with R <= C, column by column: C = c holds
+// R = 0 .. c, so pairs before column c number c (c + 1) / 2.
+__host__ __device__ __forceinline__ void tri_pair(uint64_t w, uint32_t* r, uint32_t* c) {
+  uint64_t cc = (uint64_t)((__builtin_sqrt(8.0 * (double)w + 1.0) - 1.0) * 0.5);
+  while ((cc + 1) * (cc + 2) / 2 <= w) ++cc;
+  while (cc * (cc + 1) / 2 > w) --cc;
+  *c = (uint32_t)cc;
+  *r = (uint32_t)(w - cc * (cc + 1) / 2);
+}
+
+template <int S, int B, bool VEC, int NT>
+__device__ __forceinline__ void tile_pair_transpose(typename Bytes<S>::T* __restrict__ base, int h,
+                                                    uint32_t tr, uint32_t tc,
+                                                    typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  const uint64_t rowstride = 1ull << h;
+  // tile (R, C) starts at row R 2^b, column C 2^b; tile_load's "y" selects
+  // the column block, so pass the row block through the base pointer
+  typename Bytes<S>::T* a = base + ((uint64_t)tr << (B + h));
+  typename Bytes<S>::T* b = base + ((uint64_t)tc << (B + h));
+  const bool diag = (tr == tc);
+  Chunk<S, Sh::VB> ra[PT], rb[PT];
+  tile_load<S, B, VEC, NT, PT>(ra, a, rowstride, tc);
+  if (!diag) tile_load<S, B, VEC, NT, PT>(rb, b, rowstride, tr);
+  tile_scatter<S, B, VEC, NT, PT, false>(ra, lds);
+  if (!diag) tile_scatter<S, B, VEC, NT, PT, false>(rb, lds + Sh::TILE_E);
+  __syncthreads();
+  tile_store<S, B, VEC, NT, PT>(b, rowstride, tr, lds);
+  if (!diag) tile_store<S, B, VEC, NT, PT>(a, rowstride, tc, lds + Sh::TILE_E);
 }
 
 // ---------------------------------------------------------------------------

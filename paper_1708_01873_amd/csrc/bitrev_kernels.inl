@@ -154,6 +154,22 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
   }
 }
 
+// In-place transpose of a 2^h x 2^h matrix: work item -> tile pair
+// (R <= C) -> swap (R, C) and (C, R) through LDS.
+template <int S, int B, bool VEC>
+__global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_transpose_inplace(
+    void* data, int h, uint64_t total_items, int xcds) {
+  typedef typename Bytes<S>::T E;
+  constexpr int NT = tile_threads<S, B, VEC>();
+  __shared__ E lds[2 * TileShape<S, B, VEC>::TILE_E];
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    uint32_t tr, tc;
+    tri_pair(item, &tr, &tc);
+    tile_pair_transpose<S, B, VEC, NT>(static_cast<E*>(data), h, tr, tc, lds);
+    __syncthreads();
+  }
+}
+
 // n = 2^k <= 64: one wavefront per array, four arrays per workgroup.
 template <int S>
 __global__ __launch_bounds__(256) void k_wave(const void* src, void* dst, int k, uint64_t nseg) {
@@ -281,6 +297,23 @@ hipError_t dispatch_tile(bool inplace, int b, bool vec, const TileLaunch& a, hip
   }
 }
 
+template <int S, int B, bool VEC>
+hipError_t run_transpose(const TransposeLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_transpose_inplace<S, B, VEC>), dim3(a.grid),
+                     dim3(tile_threads<S, B, VEC>()), 0, st, a.data, a.h, a.total_items, a.xcds);
+  return hipGetLastError();
+}
+
+template <int S, int B = 0>
+hipError_t dispatch_transpose(int b, bool vec, const TransposeLaunch& a, hipStream_t st) {
+  if constexpr (B > max_tile_bits(S)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (b == B) return vec ? run_transpose<S, B, true>(a, st) : run_transpose<S, B, false>(a, st);
+    return dispatch_transpose<S, B + 1>(b, vec, a, st);
+  }
+}
+
 template <int S, int B = kMinBatchedTileBits>
 hipError_t dispatch_batched(const BatchedLaunch& a, hipStream_t st) {
   if constexpr (B > max_tile_bits(S)) {
@@ -329,6 +362,11 @@ hipError_t BITREV_CAT(launch_tile_outofplace_s, BITREV_S)(int b, bool vec, const
 hipError_t BITREV_CAT(launch_wave_s, BITREV_S)(const WaveLaunch& a, hipStream_t st) {
   hipLaunchKernelGGL((k_wave<BITREV_S>), dim3(a.grid), dim3(256), 0, st, a.src, a.dst, a.k, a.nseg);
   return hipGetLastError();
+}
+
+hipError_t BITREV_CAT(launch_transpose_s, BITREV_S)(int b, bool vec, const TransposeLaunch& a,
+                                                    hipStream_t st) {
+  return dispatch_transpose<BITREV_S>(b, vec, a, st);
 }
 
 hipError_t BITREV_CAT(launch_batched_s, BITREV_S)(const BatchedLaunch& a, hipStream_t st) {

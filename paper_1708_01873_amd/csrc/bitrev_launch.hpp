@@ -37,6 +37,14 @@ struct WaveLaunch {
   uint32_t grid;
 };
 
+struct TransposeLaunch {
+  void* data;
+  int h;                    // the matrix is 2^h x 2^h elements
+  uint64_t total_items;     // tile pairs (R <= C)
+  int xcds;
+  uint32_t grid;
+};
+
 struct BatchedLaunch {
   void* data;
   const int64_t* offsets;
@@ -64,6 +72,8 @@ size_t tile_lds_bytes(int s, int b, bool inplace);
                                          hipStream_t st);                            \
   hipError_t launch_wave_s##S(const WaveLaunch& a, hipStream_t st);                  \
   hipError_t launch_batched_s##S(const BatchedLaunch& a, hipStream_t st);            \
+  hipError_t launch_transpose_s##S(int b, bool vec, const TransposeLaunch& a,        \
+                                   hipStream_t st);                                  \
   int tile_threads_s##S(int b, bool vec);                                            \
   int tile_occupancy_s##S(int b, bool vec, bool inplace, bool pipelined);            \
   int batched_threads_s##S(int b);

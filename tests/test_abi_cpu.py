@@ -233,3 +233,31 @@ def test_spread_is_a_bijection(L, width):
     for t in range(width):
         want = (t // 2) if t % 2 == 0 else (width - 1 - t // 2)
         assert L.bitrev_debug_spread(1 << t, width) == 1 << want, (width, t)
+
+
+def test_recursive_and_transpose_validation(L):
+    assert L.bitrev_inplace_recursive(FAKE, 23, 8, None) == br.ERROR_NOT_SUPPORTED
+    assert L.bitrev_inplace_recursive(None, 24, 8, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_inplace_recursive(FAKE, 24, 12, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_inplace_recursive(FAKE + 4, 24, 8, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_inplace_recursive(FAKE, 0, 8, None) == br.SUCCESS
+    assert L.bitrev_transpose_inplace(FAKE, 21, 8, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_transpose_inplace(FAKE, -1, 8, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_transpose_inplace(None, 4, 8, None) == br.ERROR_INVALID_VALUE
+
+
+def test_triangular_tile_pairs(L):
+    """The transpose kernel's tile pairs cover r <= c exactly once, in order,
+    including indices large enough to stress the square-root estimate."""
+    r, c = ctypes.c_uint32(), ctypes.c_uint32()
+    w = 0
+    for cc in range(0, 300):
+        for rr in range(0, cc + 1):
+            L.bitrev_debug_tri_pair(w, ctypes.byref(r), ctypes.byref(c))
+            assert (r.value, c.value) == (rr, cc), w
+            w += 1
+    for cc in (2**15 - 1, 2**16 - 1, 2**19 - 3, 2**20 - 1):
+        base = cc * (cc + 1) // 2
+        for rr in (0, 1, cc // 2, cc):
+            L.bitrev_debug_tri_pair(base + rr, ctypes.byref(r), ctypes.byref(c))
+            assert (r.value, c.value) == (rr, cc)
