@@ -191,6 +191,27 @@ bitrev_status_t bitrev_load_tuning(const char* path);
 const char* bitrev_tuning_format(void);
 
 /* ------------------------------------------------------------------------ */
+/* Bit reversal fused with the first FFT levels                              */
+/* ------------------------------------------------------------------------ */
+
+/* `rows` arrays of 2^log2n complex elements (dtype 0: complex64, two float32;
+ * 1: complex128, two float64; interleaved real, imaginary), each replaced by
+ * its bit-reversed permutation followed by the first `stages` levels of a
+ * radix-2 decimation-in-time FFT (the paper's motivation, Introduction: the
+ * reversal performs all even-odd splits up front, after which each FFT level
+ * works on contiguous blocks).  Afterwards every block of 2^stages
+ * consecutive outputs J holds the length-2^stages DFT of the subsequence
+ * x[rev(J) + 2^(log2n - stages) u], u = 0 .. 2^stages - 1, with twiddles
+ * exp(-2 pi i / 2^s) (inverse = 1: exp(+2 pi i / 2^s), unscaled).  The levels
+ * run on the tile rows staged in LDS, so the HBM traffic is that of the plain
+ * permutation.  src == dst is in place; otherwise the ranges must not overlap.
+ * 0 <= stages <= min(floor(log2n / 2), 6), else BITREV_ERROR_NOT_SUPPORTED;
+ * stages = 0 is bitrev_rows.  Arithmetic in the element's precision with
+ * twiddles rounded once from double precision. */
+bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t rows, int stages,
+                                  int inverse, int dtype, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* The paper's recursive scheme, as an A/B baseline for the one-pass kernels */
 /* ------------------------------------------------------------------------ */
 

@@ -81,6 +81,7 @@ _SIGNATURES = {
     "bitrev_tuning_format": ([], ctypes.c_char_p),
     "bitrev_copy": ([_VP, _VP, _SZ, _VP], _I),
     "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
+    "bitrev_dit_stages": ([_VP, _VP, _I, _I64, _I, _I, _I, _VP], _I),
     "bitrev_transpose_inplace": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_status_string": ([_I], ctypes.c_char_p),
     "bitrev_last_hip_error": ([], _I),
@@ -289,6 +290,30 @@ def bitrev_copy(src, dst, stream=None):
     return dst
 
 
+def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, log2n=None,
+                      stream=None):
+    """Bit reversal of each row (last dimension, complex64 or complex128)
+    followed by the first `stages` radix-2 DIT FFT levels; ``dst is src``
+    works in place.  Allocates ``dst`` when not given."""
+    import torch
+    if src.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("bitrev_dit_stages needs complex64 or complex128 data")
+    if dst is None:
+        dst = torch.empty_like(src)
+    if dst.dtype != src.dtype or dst.numel() != src.numel():
+        raise ValueError("src and dst must have the same dtype and length")
+    sp, _ = _tensor_args(src, "src")
+    dp, _ = _tensor_args(dst, "dst")
+    k = _log2_exact(src.shape[-1]) if log2n is None else int(log2n)
+    rows = src.numel() >> k
+    if rows << k != src.numel():
+        raise ValueError("not a whole number of rows")
+    dtype = 0 if src.dtype == torch.complex64 else 1
+    _check(_load().bitrev_dit_stages(sp, dp, k, rows, int(stages), 1 if inverse else 0, dtype,
+                                     _stream(stream)), "bitrev_dit_stages")
+    return dst
+
+
 def bitrev_inplace_recursive(data, log2n: Optional[int] = None, *, stream=None):
     """In place by the paper's recursive scheme (three passes: block-local
     reversals, square transpose, block-local reversals); log2n must be even.
@@ -339,5 +364,5 @@ __all__ = [
     "bitrev_inplace", "bitrev_outofplace", "bitrev_rows", "bitrev_batched",
     "bitrev_batched_workspace_size", "bitrev_batched_errors", "bitrev_copy",
     "bitrev_plan_query", "bitrev_load_tuning", "bitrev_tuning_format",
-    "bitrev_inplace_recursive", "bitrev_transpose_inplace",
+    "bitrev_inplace_recursive", "bitrev_transpose_inplace", "bitrev_dit_stages",
 ]

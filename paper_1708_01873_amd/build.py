@@ -27,8 +27,9 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
-    # Keep the compiler from emitting packed FP32 instructions; this code has
-    # no float arithmetic, the flag guards against it ever appearing.
+    "-fno-strict-aliasing",
+    # Keep the compiler from emitting packed FP32 instructions (the fused FFT
+    # levels are the only float arithmetic; they must not use them).
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,
     "-I", CSRC,

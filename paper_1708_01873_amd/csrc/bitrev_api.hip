@@ -483,6 +483,54 @@ bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_s
   return run_transpose(data, log2side, elem_size, static_cast<hipStream_t>(stream));
 }
 
+bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t rows, int stages,
+                                  int inverse, int dtype, void* stream) {
+  // ---- validation: no HIP call before this block completes ----
+  if (src == NULL || dst == NULL || log2n < 0 || log2n > BITREV_MAX_LOG2N || rows < 0 ||
+      stages < 0 || stages > 7 || (inverse != 0 && inverse != 1) || (dtype != 0 && dtype != 1))
+    return BITREV_ERROR_INVALID_VALUE;
+  const size_t s = dtype == 0 ? 8 : 16;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % s)
+    return BITREV_ERROR_INVALID_VALUE;
+  const uint64_t n = 1ull << log2n;
+  if (rows > 0 && (uint64_t)rows > (1ull << 62) / (n * s)) return BITREV_ERROR_INVALID_VALUE;
+  const bool inplace = (src == dst);
+  if (!inplace && overlap(src, dst, (size_t)(n * s * (uint64_t)rows))) return BITREV_ERROR_ALIAS;
+  if (2 * stages > log2n || stages > max_tile_bits((int)s)) return BITREV_ERROR_NOT_SUPPORTED;
+  if (stages == 0) return run_plain(src, dst, log2n, rows, s, NULL, stream, true);
+  if (rows == 0) return BITREV_SUCCESS;
+  // ---- plan and launch ----
+  DeviceInfo d;
+  bitrev_status_t st = device_info(&d, false);
+  if (st != BITREV_SUCCESS) return st;
+  int b = default_plan(inplace ? 0 : 1, (int)s, n * s).b;
+  if (b < stages) b = stages;
+  if (b > max_tile_bits((int)s)) b = max_tile_bits((int)s);
+  if (2 * b > log2n) b = log2n / 2;
+  const size_t lds = tile_lds_bytes_for((int)s, b, 2) + ((size_t)1 << b) * (s / 2);
+  if (b < stages || lds > d.lds_per_block) return BITREV_ERROR_NOT_SUPPORTED;
+  const int m = log2n - 2 * b;
+  if (m > 32) return BITREV_ERROR_NOT_SUPPORTED;
+  DitLaunch a;
+  a.t.src = src;
+  a.t.dst = dst;
+  a.t.m = m;
+  a.t.items_per_seg = inplace ? pair_count(m) : (1ull << m);
+  a.t.total_items = a.t.items_per_seg * (uint64_t)rows;
+  a.t.seg_elems = n;
+  a.t.balanced = 1;
+  a.t.xcds = d.xcds;
+  a.t.grid = default_grid(a.t.total_items, d);
+  a.t.pipelined = 0;
+  a.stages = stages;
+  a.inverse = inverse;
+  const size_t vb = (s << b) < 16 ? (s << b) : 16;
+  const bool vec = pointer_align(src, dst) % vb == 0;
+  const hipError_t e = s == 8 ? launch_dit_s8(b, vec, a, static_cast<hipStream_t>(stream))
+                              : launch_dit_s16(b, vec, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
 bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size, void* stream) {
   if (data == NULL || log2n < 0 || log2n > BITREV_MAX_LOG2N || !valid_elem_size(elem_size) ||
       reinterpret_cast<uintptr_t>(data) % elem_size)

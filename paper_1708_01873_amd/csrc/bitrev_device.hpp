@@ -257,6 +257,66 @@ __device__ __forceinline__ void tile_outofplace(const typename Bytes<S>::T* __re
 }
 
 // ---------------------------------------------------------------------------
+// Fused first FFT levels.  After the reversal, a radix-2 decimation-in-time
+// FFT works on contiguous blocks (Introduction: every even-odd split done up
+// front is the bit-reversed permutation).  Each LDS row of a staged tile is a
+// contiguous run of 2^b outputs starting at a multiple of 2^b, so the first
+// L <= b levels run on the staged rows before they are written: the blocks
+// of 2^L outputs leave as length-2^L DFTs, at no extra HBM traffic.
+// ---------------------------------------------------------------------------
+template <int S> struct ComplexOf;
+template <> struct ComplexOf<8> { typedef float T; };
+template <> struct ComplexOf<16> { typedef double T; };
+
+// Twiddles w_R^t = exp(-2 pi i t / R), t < R/2, for R = 2^B, computed in
+// double precision and rounded once to the element's precision.
+template <int S, int B, int NT>
+__device__ __forceinline__ void make_twiddles(typename ComplexOf<S>::T* tw) {
+  typedef typename ComplexOf<S>::T F;
+  for (int t = (int)threadIdx.x; t < (1 << B) / 2; t += NT) {
+    double sn, cs;
+    sincospi(-2.0 * (double)t / (double)(1 << B), &sn, &cs);
+    tw[2 * t] = (F)cs;
+    tw[2 * t + 1] = (F)sn;
+  }
+}
+
+// Levels 1 .. stages of the radix-2 DIT butterflies on `rows` staged rows:
+// for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b), w = exp(-+ 2 pi i / 2^s)
+// (sign + for the inverse).  A barrier ends each level.
+template <int S, int B, int NT>
+__device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, int stages,
+                                         bool inverse, const typename ComplexOf<S>::T* tw) {
+  typedef typename ComplexOf<S>::T F;
+  constexpr int R = 1 << B;
+  constexpr int H = R / 2;
+  constexpr int PE = TileShape<S, B, true>::PE;
+  F* base = reinterpret_cast<F*>(lds);
+  for (int s = 1; s <= stages; ++s) {
+    const int half = 1 << (s - 1);
+    const int tstride = R >> s;
+    for (int beta = (int)threadIdx.x; beta < rows * H; beta += NT) {
+      const int row = beta / H;
+      const int tp = beta % H;
+      const int t = tp & (half - 1);
+      const int c0 = ((tp >> (s - 1)) << s) + t;
+      F* pa = base + 2 * (row * PE + c0);
+      F* pb = pa + 2 * half;
+      const F wr = tw[2 * t * tstride];
+      const F wi = inverse ? -tw[2 * t * tstride + 1] : tw[2 * t * tstride + 1];
+      const F ar = pa[0], ai = pa[1], br = pb[0], bi = pb[1];
+      const F tr = br * wr - bi * wi;
+      const F ti = br * wi + bi * wr;
+      pa[0] = ar + tr;
+      pa[1] = ai + ti;
+      pb[0] = ar - tr;
+      pb[1] = ai - ti;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // In-place square transpose (the middle step of the paper's recursive
 // method, Methods): a 2^h x 2^h matrix in 2^b x 2^b tiles; tiles (R, C) and
 // (C, R) swap through LDS, each transposed; diagonal tiles transpose alone.

@@ -170,6 +170,75 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_transpose_inpla
   }
 }
 
+#if BITREV_S == 8 || BITREV_S == 16
+// Bit reversal fused with the first `stages` radix-2 DIT levels (complex
+// elements), out of place (src != dst) or in place (src == dst, tile pairs).
+template <int S, int B, bool VEC>
+__global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
+    const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
+    uint64_t seg_elems, int stages, int inverse, int xcds) {
+  typedef typename Bytes<S>::T E;
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename ComplexOf<S>::T F;
+  constexpr int NT = tile_threads<S, B, VEC>();
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  __shared__ E lds[2 * Sh::TILE_E];
+  __shared__ F tw[(1 << B) > 1 ? (1 << B) : 2];
+  make_twiddles<S, B, NT>(tw);
+  const bool inplace = (src == dst);
+  const uint64_t rowstride = 1ull << (m + B);
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    uint64_t seg = 0, local = item;
+    if (items_per_seg != total_items) {
+      seg = item / items_per_seg;
+      local = item - seg * items_per_seg;
+    }
+    const E* in = static_cast<const E*>(src) + seg * seg_elems;
+    E* out = static_cast<E*>(dst) + seg * seg_elems;
+    Chunk<S, Sh::VB> ra[PT], rb[PT];
+    if (inplace) {
+      const uint32_t y = pair_at(m, local, true);
+      const uint32_t yr = rev_bits(y, m);
+      const bool pal = (y == yr);
+      tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
+      if (!pal) tile_load<S, B, VEC, NT, PT>(rb, in, rowstride, yr);
+      tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+      if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+      __syncthreads();
+      dit_rows<S, B, NT>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw);
+      tile_store<S, B, VEC, NT, PT>(out, rowstride, yr, lds);
+      if (!pal) tile_store<S, B, VEC, NT, PT>(out, rowstride, y, lds + Sh::TILE_E);
+    } else {
+      const uint32_t y = spread_bits((uint32_t)local, m);
+      tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
+      tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+      __syncthreads();
+      dit_rows<S, B, NT>(lds, Sh::R, stages, inverse != 0, tw);
+      tile_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
+    }
+    __syncthreads();
+  }
+}
+
+template <int S, int B, bool VEC>
+hipError_t run_dit(const DitLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_tile_dit<S, B, VEC>), dim3(a.t.grid), dim3(tile_threads<S, B, VEC>()), 0,
+                     st, a.t.src, a.t.dst, a.t.m, a.t.items_per_seg, a.t.total_items,
+                     a.t.seg_elems, a.stages, a.inverse, a.t.xcds);
+  return hipGetLastError();
+}
+
+template <int S, int B = 1>
+hipError_t dispatch_dit(int b, bool vec, const DitLaunch& a, hipStream_t st) {
+  if constexpr (B > max_tile_bits(S)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (b == B) return vec ? run_dit<S, B, true>(a, st) : run_dit<S, B, false>(a, st);
+    return dispatch_dit<S, B + 1>(b, vec, a, st);
+  }
+}
+#endif
+
 // n = 2^k <= 64: one wavefront per array, four arrays per workgroup.
 template <int S>
 __global__ __launch_bounds__(256) void k_wave(const void* src, void* dst, int k, uint64_t nseg) {
@@ -368,6 +437,12 @@ hipError_t BITREV_CAT(launch_transpose_s, BITREV_S)(int b, bool vec, const Trans
                                                     hipStream_t st) {
   return dispatch_transpose<BITREV_S>(b, vec, a, st);
 }
+
+#if BITREV_S == 8 || BITREV_S == 16
+hipError_t BITREV_CAT(launch_dit_s, BITREV_S)(int b, bool vec, const DitLaunch& a, hipStream_t st) {
+  return dispatch_dit<BITREV_S>(b, vec, a, st);
+}
+#endif
 
 hipError_t BITREV_CAT(launch_batched_s, BITREV_S)(const BatchedLaunch& a, hipStream_t st) {
   return dispatch_batched<BITREV_S>(a, st);

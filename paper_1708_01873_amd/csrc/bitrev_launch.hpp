@@ -37,6 +37,12 @@ struct WaveLaunch {
   uint32_t grid;
 };
 
+struct DitLaunch {
+  TileLaunch t;             // the tile geometry (src == dst: in place)
+  int stages;               // DIT levels fused after the reversal, <= b
+  int inverse;              // 1: exp(+2 pi i ...) twiddles
+};
+
 struct TransposeLaunch {
   void* data;
   int h;                    // the matrix is 2^h x 2^h elements
@@ -83,6 +89,9 @@ BITREV_DECLARE_LAUNCHERS(2)
 BITREV_DECLARE_LAUNCHERS(4)
 BITREV_DECLARE_LAUNCHERS(8)
 BITREV_DECLARE_LAUNCHERS(16)
+
+hipError_t launch_dit_s8(int b, bool vec, const DitLaunch& a, hipStream_t st);
+hipError_t launch_dit_s16(int b, bool vec, const DitLaunch& a, hipStream_t st);
 
 hipError_t launch_batched_prep(const BatchedLaunch& a, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, uint32_t grid, hipStream_t st);

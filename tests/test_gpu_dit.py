@@ -1,0 +1,77 @@
+"""Bit reversal fused with the first L radix-2 DIT levels vs the oracle's
+closed form.  The tolerance is Higham's norm-wise bound for an L-level
+radix-2 FFT in the element's precision (twiddles rounded once), applied to
+every block of 2^L outputs."""
+import numpy as np
+import pytest
+
+import paper_1708_01873_amd as br
+from gpu_util import to_host_bytes
+from oracle import dit
+from paper_1708_01873_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = {np.complex64: 2.0 ** -24, np.complex128: 2.0 ** -53}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    br.lib()
+
+
+def _check(got, x, L, inverse, dtype):
+    want = dit.dit_stages(x, L, inverse)
+    q = 1 << L
+    g = got.astype(np.complex128).reshape(-1, q)
+    w = want.reshape(-1, q)
+    err = np.linalg.norm(g - w, axis=1)
+    ref = np.linalg.norm(w, axis=1)
+    bound = dit.higham_bound(L, U[dtype], U[dtype])
+    # the inputs are exact in the element type, so the bound applies as is
+    assert np.all(err <= bound * ref + 1e-30), (float((err / np.maximum(ref, 1e-300)).max()), bound)
+
+
+def _data(k, rows, dtype, seed):
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal(rows << k)
+    im = rng.standard_normal(rows << k)
+    return (re + 1j * im).astype(dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_dit_stages_sweep(dtype):
+    for k in (2, 5, 8, 11, 14, 17):
+        for L in range(0, min(k // 2, 6) + 1):
+            x = _data(k, 1, dtype, 10 * k + L)
+            for inverse in (False, True):
+                t = torch.from_numpy(x).cuda()
+                y = br.bitrev_dit_stages(t, stages=L, inverse=inverse)
+                _check(to_host_bytes(y).view(dtype), x, L, inverse, dtype)
+                br.bitrev_dit_stages(t, t, stages=L, inverse=inverse)  # in place
+                _check(to_host_bytes(t).view(dtype), x, L, inverse, dtype)
+
+
+def test_dit_rows_and_full_size():
+    """Many rows, and the complex64 2^24 array at six fused levels."""
+    x = _data(12, 9, np.complex64, 3).reshape(9, 1 << 12)
+    y = br.bitrev_dit_stages(torch.from_numpy(x).cuda(), stages=6)
+    got = to_host_bytes(y).view(np.complex64).reshape(9, -1)
+    for r in range(9):
+        _check(got[r], x[r], 6, False, np.complex64)
+    x = workloads.complex64_normal(24, workloads.SEEDS["c2"])
+    t = torch.from_numpy(x).cuda()
+    br.bitrev_dit_stages(t, t, stages=6)
+    _check(to_host_bytes(t).view(np.complex64), x, 6, False, np.complex64)
+
+
+def test_dit_rejects():
+    t = torch.zeros(1 << 10, dtype=torch.complex64, device="cuda")
+    with pytest.raises(br.BitrevError) as e:
+        br.bitrev_dit_stages(t, stages=6)  # 2 * 6 > 10
+    assert e.value.status == br.ERROR_NOT_SUPPORTED
+    with pytest.raises(TypeError):
+        br.bitrev_dit_stages(torch.zeros(16, device="cuda"), stages=1)
