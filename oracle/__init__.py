@@ -69,6 +69,14 @@ class Oracle:
                                      ctypes.c_int64, ctypes.c_size_t]
         L.oracle_batched.restype = ctypes.c_int
         L.oracle_version.restype = ctypes.c_int
+        L.oracle_digit_rev.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
+        L.oracle_digit_rev.restype = ctypes.c_uint64
+        L.oracle_digit_outofplace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_size_t]
+        L.oracle_digit_outofplace.restype = ctypes.c_int
+        L.oracle_digit_inplace.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_size_t]
+        L.oracle_digit_inplace.restype = ctypes.c_int
         self.lib = L
         self.path = path
 
@@ -129,6 +137,26 @@ class Oracle:
             raise ValueError("oracle_batched rejected its arguments")
         return data
 
+    def digit_rev(self, i: int, k: int, d: int) -> int:
+        """Reverse the order of the d-bit digits of the k-bit index i."""
+        return int(self.lib.oracle_digit_rev(int(i), int(k), int(d)))
+
+    def digit_outofplace(self, a: np.ndarray, d: int, elem_size: int | None = None) -> np.ndarray:
+        """dst[drev(i)] = a[i], digits of d bits."""
+        s, n = self._elems(a, elem_size)
+        k = _log2_exact(n)
+        out = np.empty_like(a)
+        if self.lib.oracle_digit_outofplace(a.ctypes.data, out.ctypes.data, k, d, s) != 0:
+            raise ValueError("oracle_digit_outofplace rejected its arguments")
+        return out
+
+    def digit_inplace(self, a: np.ndarray, d: int, elem_size: int | None = None) -> np.ndarray:
+        s, n = self._elems(a, elem_size)
+        k = _log2_exact(n)
+        if self.lib.oracle_digit_inplace(a.ctypes.data, k, d, s) != 0:
+            raise ValueError("oracle_digit_inplace rejected its arguments")
+        return a
+
     def rev_table(self, k: int) -> np.ndarray:
         """rev_k(j) for every j, read off the in-place permutation of 0..n-1."""
         return self.inplace(np.arange(1 << k, dtype=np.int64))
@@ -168,3 +196,15 @@ def batched(data, offsets, log2n, elem_size=None):
 
 def rev_table(k: int) -> np.ndarray:
     return default().rev_table(k)
+
+
+def digit_rev(i: int, k: int, d: int) -> int:
+    return default().digit_rev(i, k, d)
+
+
+def digit_outofplace(a, d, elem_size=None):
+    return default().digit_outofplace(a, d, elem_size)
+
+
+def digit_inplace(a, d, elem_size=None):
+    return default().digit_inplace(a, d, elem_size)

@@ -140,4 +140,52 @@ int oracle_batched(void *data, const int64_t *offsets, const int32_t *log2n,
     return 0;
 }
 
+/* Digit reversal for radix-2^d FFTs (the paper's Introduction motivates the
+ * permutation by radix-2 decimation in time; a radix-2^d FFT splits by 2^d
+ * residues at each level, and doing those splits up front reverses the order
+ * of the base-2^d digits of each index).  k must be a multiple of d; the
+ * digits are d-bit groups, least significant first, and their order is
+ * reversed while each digit keeps its own bit order.  d = 1 is oracle_rev. */
+uint64_t oracle_digit_rev(uint64_t i, int k, int d)
+{
+    uint64_t r = 0, mask;
+    int j;
+    if (d <= 0 || k % d)
+        return ~(uint64_t)0;
+    mask = ((uint64_t)1 << d) - 1;
+    for (j = 0; j < k; j += d)
+        r = (r << d) | ((i >> j) & mask);
+    return r;
+}
+
+/* Out of place digit-reversed permutation: dst[drev(i)] <- src[i]. */
+int oracle_digit_outofplace(const void *src, void *dst, int k, int d, size_t elem_size)
+{
+    const unsigned char *in = (const unsigned char *)src;
+    unsigned char *out = (unsigned char *)dst;
+    uint64_t n, i;
+    if (k < 0 || k > ORACLE_MAX_LOG2N || d <= 0 || k % d || elem_size == 0 || !src || !dst)
+        return -1;
+    n = (uint64_t)1 << k;
+    for (i = 0; i < n; ++i)
+        memcpy(out + oracle_digit_rev(i, k, d) * elem_size, in + i * elem_size, elem_size);
+    return 0;
+}
+
+/* In place: digit reversal is an involution too, so swap each pair once. */
+int oracle_digit_inplace(void *data, int k, int d, size_t elem_size)
+{
+    unsigned char *v = (unsigned char *)data;
+    uint64_t n, i;
+    if (k < 0 || k > ORACLE_MAX_LOG2N || d <= 0 || k % d || elem_size == 0 || (!data && k > 0))
+        return -1;
+    n = (uint64_t)1 << k;
+    for (i = 0; i < n; ++i) {
+        uint64_t r = oracle_digit_rev(i, k, d);
+        if (i < r)
+            swap_bytes(v + i * elem_size, v + r * elem_size, elem_size);
+    }
+    return 0;
+}
+
 int oracle_version(void) { return 1; }

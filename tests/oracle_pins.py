@@ -225,3 +225,47 @@ ALL_PINS = [
     pin_special_values,
     pin_rows_and_batched,
 ]
+
+
+def _digits(i: int, k: int, d: int) -> list:
+    """Base-2^d digits of i, least significant first, by integer division."""
+    q = 1 << d
+    return [(i // q ** t) % q for t in range(k // d)]
+
+
+def pin_digit_reversal(o) -> None:
+    """Digit reversal for radix-2^d FFTs: d = 1 is the bit reversal; the
+    digit list reversed (by divmod, independent of shifts); an involution;
+    fixed points q^ceil(D/2); base 4 on n = 16 by hand."""
+    # base 4, n = 16 (two digits): index 1 = (0,1) -> (1,0) = 4, 6 = (1,2) -> (2,1) = 9
+    want16 = [0, 4, 8, 12, 1, 5, 9, 13, 2, 6, 10, 14, 3, 7, 11, 15]
+    assert [o.digit_rev(i, 4, 2) for i in range(16)] == want16
+    for d in (1, 2, 3):
+        for k in range(0, 13, d):
+            if k % d:
+                continue
+            n, q, D = 1 << k, 1 << d, k // d
+            want = []
+            for i in range(n):
+                dg = _digits(i, k, d)[::-1]
+                want.append(sum(v * q ** t for t, v in enumerate(dg)))
+            got = [o.digit_rev(i, k, d) for i in range(n)]
+            assert got == want, (d, k)
+            if d == 1:
+                assert got == [rev_bytetable(i, k) for i in range(n)]
+            assert all(got[got[i]] == i for i in range(n))
+            assert sum(1 for i in range(n) if got[i] == i) == q ** ((D + 1) // 2)
+            a = np.arange(n, dtype=np.int64)
+            assert np.array_equal(o.digit_outofplace(a, d), np.array(want).argsort()), (d, k)
+            b = a.copy()
+            o.digit_inplace(b, d)
+            assert np.array_equal(b, np.array(want)), (d, k)
+    try:
+        o.digit_outofplace(np.arange(8, dtype=np.int64), 2)  # k = 3 is not a multiple of 2
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("digit reversal accepted k not a multiple of d")
+
+
+ALL_PINS.append(pin_digit_reversal)

@@ -29,6 +29,9 @@ MUTANTS = [
     ("batched_offsets_in_bytes", "(size_t)offsets[a] * elem_size", "(size_t)offsets[a]"),
     ("batched_skips_last_array", "for (a = 0; a < num_arrays; ++a)",
      "for (a = 0; a + 1 < num_arrays; ++a)"),
+    ("digits_reversed_bitwise", "r = (r << d) | ((i >> j) & mask);",
+     "r = (r << d) | oracle_rev((i >> j) & mask, d);"),
+    ("digit_dropped", "for (j = 0; j < k; j += d)", "for (j = d; j < k; j += d)"),
 ]
 
 
