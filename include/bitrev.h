@@ -191,6 +191,24 @@ bitrev_status_t bitrev_load_tuning(const char* path);
 const char* bitrev_tuning_format(void);
 
 /* ------------------------------------------------------------------------ */
+/* Digit reversal for radix-4 and radix-8 FFTs                               */
+/* ------------------------------------------------------------------------ */
+
+/* The permutation a radix-2^d decimation-in-time FFT needs: the order of the
+ * d-bit digits of each index is reversed (each digit keeps its bits); the
+ * paper's bit reversal is d = 1 (Introduction: the reversal performs the
+ * FFT's recursive index splits up front -- a radix-2^d FFT splits by 2^d
+ * residues per level).  It is an involution too, so in place it swaps pairs.
+ * digit_bits in {1, 2, 3}; log2n must be a multiple of digit_bits, else
+ * BITREV_ERROR_INVALID_VALUE.  Other arguments as bitrev_inplace and
+ * bitrev_outofplace; same tile method with tile widths and the middle width
+ * whole numbers of digits. */
+bitrev_status_t bitrev_digitrev_inplace(void* data, int log2n, int digit_bits, size_t elem_size,
+                                        void* stream);
+bitrev_status_t bitrev_digitrev_outofplace(const void* src, void* dst, int log2n, int digit_bits,
+                                           size_t elem_size, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Bit reversal fused with the first FFT levels                              */
 /* ------------------------------------------------------------------------ */
 
@@ -259,6 +277,11 @@ uint32_t bitrev_debug_pair_at(int m, uint64_t w, int balanced);
 uint32_t bitrev_debug_spread(uint32_t w, int width);
 /* The w-th tile pair (r <= c) of the square transpose, column by column. */
 void bitrev_debug_tri_pair(uint64_t w, uint32_t* r, uint32_t* c);
+/* Digit reversal of the low j bits of v in d-bit digits (j a multiple of d). */
+uint32_t bitrev_debug_digit_rev(uint32_t v, int j, int d);
+/* Number of y in [0, 2^m) with y <= drev(y), and the w-th such y. */
+uint64_t bitrev_debug_digit_pair_count(int m, int d);
+uint32_t bitrev_debug_digit_pair_at(int m, uint64_t w, int d);
 
 #ifdef __cplusplus
 }

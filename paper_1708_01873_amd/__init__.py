@@ -82,6 +82,11 @@ _SIGNATURES = {
     "bitrev_copy": ([_VP, _VP, _SZ, _VP], _I),
     "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_dit_stages": ([_VP, _VP, _I, _I64, _I, _I, _I, _VP], _I),
+    "bitrev_digitrev_inplace": ([_VP, _I, _I, _SZ, _VP], _I),
+    "bitrev_digitrev_outofplace": ([_VP, _VP, _I, _I, _SZ, _VP], _I),
+    "bitrev_debug_digit_rev": ([ctypes.c_uint32, _I, _I], ctypes.c_uint32),
+    "bitrev_debug_digit_pair_count": ([_I, _I], ctypes.c_uint64),
+    "bitrev_debug_digit_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
     "bitrev_transpose_inplace": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_status_string": ([_I], ctypes.c_char_p),
     "bitrev_last_hip_error": ([], _I),
@@ -290,6 +295,32 @@ def bitrev_copy(src, dst, stream=None):
     return dst
 
 
+def bitrev_digitrev_inplace(data, digit_bits: int, log2n: Optional[int] = None, *, stream=None):
+    """Reverse the order of the digit_bits-bit digits of every index, in place
+    (digit_bits 2: radix-4 order, 3: radix-8 order, 1: bit reversal)."""
+    ptr, s = _tensor_args(data, "data")
+    k = _log2_exact(data.numel()) if log2n is None else int(log2n)
+    _check(_load().bitrev_digitrev_inplace(ptr, k, int(digit_bits), s, _stream(stream)),
+           "bitrev_digitrev_inplace")
+    return data
+
+
+def bitrev_digitrev_outofplace(src, dst=None, digit_bits: int = 2, log2n: Optional[int] = None, *,
+                               stream=None):
+    """dst[drev(i)] = src[i] for digits of digit_bits bits."""
+    if dst is None:
+        import torch
+        dst = torch.empty_like(src)
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2 or src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same element size and length")
+    k = _log2_exact(src.numel()) if log2n is None else int(log2n)
+    _check(_load().bitrev_digitrev_outofplace(sp, dp, k, int(digit_bits), s, _stream(stream)),
+           "bitrev_digitrev_outofplace")
+    return dst
+
+
 def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, log2n=None,
                       stream=None):
     """Bit reversal of each row (last dimension, complex64 or complex128)
@@ -365,4 +396,5 @@ __all__ = [
     "bitrev_batched_workspace_size", "bitrev_batched_errors", "bitrev_copy",
     "bitrev_plan_query", "bitrev_load_tuning", "bitrev_tuning_format",
     "bitrev_inplace_recursive", "bitrev_transpose_inplace", "bitrev_dit_stages",
+    "bitrev_digitrev_inplace", "bitrev_digitrev_outofplace",
 ]

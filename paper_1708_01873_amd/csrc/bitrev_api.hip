@@ -471,9 +471,106 @@ bitrev_status_t run_transpose(void* data, int h, size_t s, hipStream_t st) {
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
 }
 
+hipError_t launch_digit(int s, int d, int b, bool vec, const TileLaunch& a, hipStream_t st) {
+  switch (s) {
+    case 1: return launch_digit_s1(d, b, vec, a, st);
+    case 2: return launch_digit_s2(d, b, vec, a, st);
+    case 4: return launch_digit_s4(d, b, vec, a, st);
+    case 8: return launch_digit_s8(d, b, vec, a, st);
+    default: return launch_digit_s16(d, b, vec, a, st);
+  }
+}
+
+hipError_t launch_wave_digit(int s, const WaveLaunch& a, int d, hipStream_t st) {
+  switch (s) {
+    case 1: return launch_wave_digit_s1(a, d, st);
+    case 2: return launch_wave_digit_s2(a, d, st);
+    case 4: return launch_wave_digit_s4(a, d, st);
+    case 8: return launch_wave_digit_s8(a, d, st);
+    default: return launch_wave_digit_s16(a, d, st);
+  }
+}
+
+// Digit-reversed permutation (d-bit digits) of one array; src == dst in place.
+bitrev_status_t run_digit(const void* src, void* dst, int k, int d, size_t s, void* stream) {
+  // ---- validation: no HIP call before this block completes ----
+  if (src == NULL || dst == NULL || k < 0 || k > BITREV_MAX_LOG2N || !valid_elem_size(s) ||
+      d < 1 || d > 3 || k % d)
+    return BITREV_ERROR_INVALID_VALUE;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % s)
+    return BITREV_ERROR_INVALID_VALUE;
+  const uint64_t n = 1ull << k;
+  const bool inplace = (src == dst);
+  if (!inplace && overlap(src, dst, (size_t)(n * s))) return BITREV_ERROR_ALIAS;
+  if (d == 1) return run_plain(src, dst, k, 1, s, NULL, stream, false);
+  if (inplace && k <= d) return BITREV_SUCCESS;  // one digit: the identity
+  // ---- plan and launch ----
+  DeviceInfo dev;
+  bitrev_status_t st = device_info(&dev, false);
+  if (st != BITREV_SUCCESS) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (k <= 6) {
+    WaveLaunch w;
+    w.src = src;
+    w.dst = dst;
+    w.k = k;
+    w.nseg = 1;
+    w.grid = 1;
+    e = launch_wave_digit((int)s, w, d, hs);
+    return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+  }
+  int b = default_plan(inplace ? 0 : 1, (int)s, n * s).b;
+  if (b > max_tile_bits((int)s)) b = max_tile_bits((int)s);
+  if (2 * b > k) b = k / 2;
+  b -= b % d;
+  while (b >= d && tile_lds_bytes_for((int)s, b, inplace ? 2 : 2) > dev.lds_per_block) b -= d;
+  if (b < d) return BITREV_ERROR_NOT_SUPPORTED;
+  const int m = k - 2 * b;
+  if (m > 32) return BITREV_ERROR_NOT_SUPPORTED;
+  TileLaunch a;
+  a.src = src;
+  a.dst = dst;
+  a.m = m;
+  a.total_items = inplace ? dpair_count(m, d) : (1ull << m);
+  a.items_per_seg = a.total_items;
+  a.seg_elems = n;
+  a.balanced = 0;
+  a.xcds = dev.xcds;
+  a.grid = default_grid(a.total_items, dev);
+  a.pipelined = 0;
+  const size_t vb = (s << b) < 16 ? (s << b) : 16;
+  e = launch_digit((int)s, d, b, pointer_align(src, dst) % vb == 0, a, hs);
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
 }  // namespace
 
 extern "C" {
+
+bitrev_status_t bitrev_digitrev_inplace(void* data, int log2n, int digit_bits, size_t elem_size,
+                                        void* stream) {
+  return run_digit(data, data, log2n, digit_bits, elem_size, stream);
+}
+
+bitrev_status_t bitrev_digitrev_outofplace(const void* src, void* dst, int log2n, int digit_bits,
+                                           size_t elem_size, void* stream) {
+  if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;
+  return run_digit(src, dst, log2n, digit_bits, elem_size, stream);
+}
+
+uint32_t bitrev_debug_digit_rev(uint32_t v, int j, int d) {
+  return (j < 0 || j > 32 || d < 1 || d > 3) ? 0u : drev_bits(v, j, d);
+}
+
+uint64_t bitrev_debug_digit_pair_count(int m, int d) {
+  return (m < 0 || m > 32 || d < 1 || d > 3 || m % d) ? 0 : dpair_count(m, d);
+}
+
+uint32_t bitrev_debug_digit_pair_at(int m, uint64_t w, int d) {
+  if (m < 0 || m > 32 || d < 1 || d > 3 || m % d || w >= dpair_count(m, d)) return 0xFFFFFFFFu;
+  return dpair_at(m, w, d);
+}
 
 bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_size, void* stream) {
   if (data == NULL || log2side < 0 || 2 * log2side > BITREV_MAX_LOG2N || !valid_elem_size(elem_size) ||

@@ -109,6 +109,66 @@ __host__ __device__ __forceinline__ uint32_t pair_at(int m, uint64_t w, bool bal
   return y;
 }
 
+// ---------------------------------------------------------------------------
+// Digit reversal for radix-2^D FFTs: the order of the D-bit digits of an
+// index is reversed, each digit keeping its own bits.  D = 1 is rev_bits.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t drev_bits(uint32_t v, int j, int d) {
+  uint32_t r = 0;
+  const uint32_t mask = (1u << d) - 1u;
+  for (int t = 0; t < j; t += d) r = (r << d) | ((v >> t) & mask);
+  return r;
+}
+
+template <int J, int D> __host__ __device__ __forceinline__ uint32_t drev_c(uint32_t v) {
+  if constexpr (D == 1) {
+    return rev_c<J>(v);
+  } else {
+    uint32_t r = 0;
+#pragma unroll
+    for (int t = 0; t < J; t += D) r = (r << D) | ((v >> t) & ((1u << D) - 1u));
+    return r;
+  }
+}
+
+// y in [0, 2^m) with y <= drev(y): (q^(m/d) + q^ceil(m/(2d))) / 2, q = 2^d.
+__host__ __device__ __forceinline__ uint64_t dpair_count(int m, int d) {
+  const int digits = m / d;
+  return ((1ull << m) + (1ull << (d * ((digits + 1) / 2)))) >> 1;
+}
+
+// The w-th y with y <= drev(y), digits decided from the outside in: an outer
+// digit pair (top T, bottom U) with T < U makes y < drev(y) for any inner
+// digits, T > U never does, T = U defers to the inner digits -- the
+// branch-and-bound rule of the paper's unrolled method (Methods, unrolling)
+// with digits in place of bits.
+__host__ __device__ __forceinline__ uint32_t dpair_at(int m, uint64_t w, int d) {
+  const uint32_t q = 1u << d;
+  uint32_t y = 0;
+  int lo = 0;
+  int width = m;
+  while (width >= 2 * d) {
+    const int inner = width - 2 * d;
+    const uint64_t q2 = ((uint64_t)(q * (q - 1) / 2)) << inner;
+    if (w < q2) {
+      const uint32_t p = (uint32_t)(w >> inner);
+      const uint32_t u = (uint32_t)(w & ((1ull << inner) - 1));
+      uint32_t hi_d = 1;  // pairs (lo_d < hi_d) number hi_d (hi_d - 1) / 2 before hi_d
+      while ((hi_d + 1) * hi_d / 2 <= p) ++hi_d;
+      const uint32_t lo_d = p - hi_d * (hi_d - 1) / 2;
+      return y | (hi_d << lo) | (lo_d << (lo + width - d)) | (u << (lo + d));
+    }
+    w -= q2;
+    const uint32_t e = (uint32_t)(w % q);
+    w /= q;
+    y |= (e << lo) | (e << (lo + width - d));
+    lo += d;
+    width -= 2 * d;
+  }
+  if (width == d) y |= (uint32_t)w << lo;
+  return y;
+}
+
 // LDS padding per tile row, in elements: one element (at least 4 bytes)
 // staggers consecutive rows across banks for the column-wise scatter.
 __host__ __device__ constexpr int lds_pad_elems(int s) { return s >= 4 ? 1 : 4 / s; }
@@ -175,9 +235,10 @@ __device__ __forceinline__ void tile_load(Chunk<S, TileShape<S, B, VEC>::VB> (&r
 }
 
 // Scatter registers into LDS in destination order: source (x, z) goes to
-// LDS row rev_b(z), column rev_b(x) -- or, with REV = false (the plain
-// square transpose), to row z, column x.
-template <int S, int B, bool VEC, int NT, int PT, bool REV = true>
+// LDS row rev_b(z), column rev_b(x).  MAP selects the index map: 1 the bit
+// reversal, D > 1 the reversal of D-bit digits, 0 none (the plain square
+// transpose: row z, column x).
+template <int S, int B, bool VEC, int NT, int PT, int MAP = 1>
 __device__ __forceinline__ void tile_scatter(const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
                                              typename Bytes<S>::T* lds) {
   typedef TileShape<S, B, VEC> Sh;
@@ -187,11 +248,11 @@ __device__ __forceinline__ void tile_scatter(const Chunk<S, TileShape<S, B, VEC>
     if (Sh::CPT % NT == 0 || q < Sh::CPT) {
       const int x = q / Sh::CPR;
       const int zc = q % Sh::CPR;
-      const uint32_t col = REV ? rev_c<B>((uint32_t)x) : (uint32_t)x;
+      const uint32_t col = MAP ? drev_c<B, (MAP ? MAP : 1)>((uint32_t)x) : (uint32_t)x;
 #pragma unroll
       for (int j = 0; j < Sh::CE; ++j) {
         const uint32_t z = (uint32_t)(zc * Sh::CE + j);
-        const uint32_t row = REV ? rev_c<B>(z) : z;
+        const uint32_t row = MAP ? drev_c<B, (MAP ? MAP : 1)>(z) : z;
         lds[row * Sh::PE + col] = reg[i].e[j];
       }
     }
@@ -347,8 +408,8 @@ __device__ __forceinline__ void tile_pair_transpose(typename Bytes<S>::T* __rest
   Chunk<S, Sh::VB> ra[PT], rb[PT];
   tile_load<S, B, VEC, NT, PT>(ra, a, rowstride, tc);
   if (!diag) tile_load<S, B, VEC, NT, PT>(rb, b, rowstride, tr);
-  tile_scatter<S, B, VEC, NT, PT, false>(ra, lds);
-  if (!diag) tile_scatter<S, B, VEC, NT, PT, false>(rb, lds + Sh::TILE_E);
+  tile_scatter<S, B, VEC, NT, PT, 0>(ra, lds);
+  if (!diag) tile_scatter<S, B, VEC, NT, PT, 0>(rb, lds + Sh::TILE_E);
   __syncthreads();
   tile_store<S, B, VEC, NT, PT>(b, rowstride, tr, lds);
   if (!diag) tile_store<S, B, VEC, NT, PT>(a, rowstride, tc, lds + Sh::TILE_E);
@@ -378,11 +439,13 @@ __device__ __forceinline__ void small_array(const typename Bytes<S>::T* src,
 // ---------------------------------------------------------------------------
 template <int S>
 __device__ __forceinline__ void wave_array(const typename Bytes<S>::T* src,
-                                           typename Bytes<S>::T* dst, int k, int lane) {
+                                           typename Bytes<S>::T* dst, int k, int lane,
+                                           int digit = 1) {
   typedef typename Bytes<S>::T E;
   const int n = 1 << k;
   const bool live = lane < n;
-  const int from = (int)rev_bits((uint32_t)lane, k) * 4;
+  const int from = (int)(digit == 1 ? rev_bits((uint32_t)lane, k)
+                                    : drev_bits((uint32_t)lane & ((1u << k) - 1u), k, digit)) * 4;
   E v;
   if constexpr (S <= 4) {
     v = live ? src[lane] : (E)0;

@@ -239,6 +239,51 @@ hipError_t dispatch_dit(int b, bool vec, const DitLaunch& a, hipStream_t st) {
 }
 #endif
 
+// Digit reversal (radix-2^D digits), in place (src == dst: pairs
+// y <= drev(y)) or out of place; the tile width B and the middle width m are
+// whole numbers of digits, so drev([x | y | z]) = [drev(z) | drev(y) | drev(x)].
+template <int S, int B, int D, bool VEC>
+__global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_digit(
+    const void* src, void* dst, int m, uint64_t total_items, int xcds) {
+  static_assert(B % D == 0, "the tile width must be a whole number of digits");
+  typedef typename Bytes<S>::T E;
+  typedef TileShape<S, B, VEC> Sh;
+  constexpr int NT = tile_threads<S, B, VEC>();
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  __shared__ E lds[2 * Sh::TILE_E];
+  const bool inplace = (src == dst);
+  const uint64_t rowstride = 1ull << (m + B);
+  const E* in = static_cast<const E*>(src);
+  E* out = static_cast<E*>(dst);
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    Chunk<S, Sh::VB> ra[PT], rb[PT];
+    const uint32_t y = inplace ? dpair_at(m, item, D) : (uint32_t)item;
+    const uint32_t yr = drev_bits(y, m, D);
+    const bool two = inplace && (y != yr);
+    tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
+    if (two) tile_load<S, B, VEC, NT, PT>(rb, in, rowstride, yr);
+    tile_scatter<S, B, VEC, NT, PT, D>(ra, lds);
+    if (two) tile_scatter<S, B, VEC, NT, PT, D>(rb, lds + Sh::TILE_E);
+    __syncthreads();
+    tile_store<S, B, VEC, NT, PT>(out, rowstride, yr, lds);
+    if (two) tile_store<S, B, VEC, NT, PT>(out, rowstride, y, lds + Sh::TILE_E);
+    __syncthreads();
+  }
+}
+
+// Digit reversal of arrays of n = 2^k <= 64: one wavefront per array.
+template <int S>
+__global__ __launch_bounds__(256) void k_wave_digit(const void* src, void* dst, int k, int d,
+                                                    uint64_t nseg) {
+  typedef typename Bytes<S>::T E;
+  const int lane = (int)(threadIdx.x & 63u);
+  const uint64_t n = 1ull << k;
+  for (uint64_t seg = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); seg < nseg;
+       seg += (uint64_t)gridDim.x * 4) {
+    wave_array<S>(static_cast<const E*>(src) + seg * n, static_cast<E*>(dst) + seg * n, k, lane, d);
+  }
+}
+
 // n = 2^k <= 64: one wavefront per array, four arrays per workgroup.
 template <int S>
 __global__ __launch_bounds__(256) void k_wave(const void* src, void* dst, int k, uint64_t nseg) {
@@ -383,6 +428,27 @@ hipError_t dispatch_transpose(int b, bool vec, const TransposeLaunch& a, hipStre
   }
 }
 
+template <int S, int D, int B = D>
+hipError_t dispatch_digit(int b, bool vec, const TileLaunch& a, hipStream_t st) {
+  if constexpr (B > max_tile_bits(S)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (b == B) {
+      if (vec) {
+        hipLaunchKernelGGL((k_tile_digit<S, B, D, true>), dim3(a.grid),
+                           dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
+                           a.total_items, a.xcds);
+      } else {
+        hipLaunchKernelGGL((k_tile_digit<S, B, D, false>), dim3(a.grid),
+                           dim3(tile_threads<S, B, false>()), 0, st, a.src, a.dst, a.m,
+                           a.total_items, a.xcds);
+      }
+      return hipGetLastError();
+    }
+    return dispatch_digit<S, D, B + D>(b, vec, a, st);
+  }
+}
+
 template <int S, int B = kMinBatchedTileBits>
 hipError_t dispatch_batched(const BatchedLaunch& a, hipStream_t st) {
   if constexpr (B > max_tile_bits(S)) {
@@ -443,6 +509,19 @@ hipError_t BITREV_CAT(launch_dit_s, BITREV_S)(int b, bool vec, const DitLaunch& 
   return dispatch_dit<BITREV_S>(b, vec, a, st);
 }
 #endif
+
+hipError_t BITREV_CAT(launch_digit_s, BITREV_S)(int d, int b, bool vec, const TileLaunch& a,
+                                                hipStream_t st) {
+  if (d == 2) return dispatch_digit<BITREV_S, 2>(b, vec, a, st);
+  if (d == 3) return dispatch_digit<BITREV_S, 3>(b, vec, a, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t BITREV_CAT(launch_wave_digit_s, BITREV_S)(const WaveLaunch& a, int d, hipStream_t st) {
+  hipLaunchKernelGGL((k_wave_digit<BITREV_S>), dim3(a.grid), dim3(256), 0, st, a.src, a.dst, a.k, d,
+                     a.nseg);
+  return hipGetLastError();
+}
 
 hipError_t BITREV_CAT(launch_batched_s, BITREV_S)(const BatchedLaunch& a, hipStream_t st) {
   return dispatch_batched<BITREV_S>(a, st);

@@ -80,6 +80,9 @@ size_t tile_lds_bytes(int s, int b, bool inplace);
   hipError_t launch_batched_s##S(const BatchedLaunch& a, hipStream_t st);            \
   hipError_t launch_transpose_s##S(int b, bool vec, const TransposeLaunch& a,        \
                                    hipStream_t st);                                  \
+  hipError_t launch_digit_s##S(int d, int b, bool vec, const TileLaunch& a,          \
+                               hipStream_t st);                                      \
+  hipError_t launch_wave_digit_s##S(const WaveLaunch& a, int d, hipStream_t st);     \
   int tile_threads_s##S(int b, bool vec);                                            \
   int tile_occupancy_s##S(int b, bool vec, bool inplace, bool pipelined);            \
   int batched_threads_s##S(int b);

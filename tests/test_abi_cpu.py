@@ -261,3 +261,26 @@ def test_triangular_tile_pairs(L):
         for rr in (0, 1, cc // 2, cc):
             L.bitrev_debug_tri_pair(base + rr, ctypes.byref(r), ctypes.byref(c))
             assert (r.value, c.value) == (rr, cc)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_digit_pair_enumeration(L, d):
+    """Digit-reversal work items cover each pair {y, drev(y)} exactly once."""
+    for m in range(0, 19, d):
+        count = L.bitrev_debug_digit_pair_count(m, d)
+        ys = [L.bitrev_debug_digit_pair_at(m, w, d) for w in range(count)]
+        dr = [oracle.digit_rev(y, m, d) for y in ys]
+        assert len(set(ys)) == count, (m, d)
+        assert all(y < 2**m and y <= r for y, r in zip(ys, dr)), (m, d)
+        brute = sum(1 for y in range(2**m) if y <= oracle.digit_rev(y, m, d))
+        assert count == brute, (m, d)
+        for v in (0, 1, 5, 2**m - 1, 12345 % (2**m) if m else 0):
+            assert L.bitrev_debug_digit_rev(v, m, d) == oracle.digit_rev(v, m, d)
+
+
+def test_digitrev_validation(L):
+    assert L.bitrev_digitrev_inplace(FAKE, 25, 2, 8, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_digitrev_inplace(FAKE, 24, 4, 8, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_digitrev_inplace(FAKE, 24, 0, 8, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_digitrev_outofplace(FAKE, FAKE, 24, 2, 8, None) == br.ERROR_ALIAS
+    assert L.bitrev_digitrev_inplace(FAKE, 3, 3, 8, None) == br.SUCCESS  # one digit

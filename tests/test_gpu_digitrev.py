@@ -1,0 +1,53 @@
+"""Digit reversal (radix-4, radix-8 orders) vs the oracle, byte for byte."""
+import pytest
+
+import oracle
+import paper_1708_01873_amd as br
+from gpu_util import assert_bytes_equal, to_device, to_host_bytes
+from paper_1708_01873_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    br.lib()
+
+
+@pytest.mark.parametrize("s", (1, 4, 8, 16))
+@pytest.mark.parametrize("d", (1, 2, 3))
+def test_digitrev_every_k(s, d):
+    for k in range(0, 22, d):
+        host = workloads.byte_pattern((1 << k) * s, seed=31 * k + d + s)
+        want = oracle.digit_outofplace(host, d, s)
+        x = to_device(host, s)
+        y = br.bitrev_digitrev_outofplace(x, None, d, k)
+        assert_bytes_equal(to_host_bytes(y), want, "oop s=%d d=%d k=%d" % (s, d, k))
+        assert_bytes_equal(to_host_bytes(x), host, "source untouched")
+        br.bitrev_digitrev_inplace(x, d, k)
+        assert_bytes_equal(to_host_bytes(x), want, "ip s=%d d=%d k=%d" % (s, d, k))
+
+
+def test_digitrev_complex64_2p24():
+    host = workloads.complex64_normal(24, workloads.SEEDS["c2"])
+    for d in (2, 3):
+        want = oracle.digit_outofplace(host, d)
+        x = torch.from_numpy(host).cuda()
+        y = br.bitrev_digitrev_outofplace(x, None, d)
+        assert_bytes_equal(to_host_bytes(y), want, "c2 digits d=%d oop" % d)
+        br.bitrev_digitrev_inplace(x, d)
+        assert_bytes_equal(to_host_bytes(x), want, "c2 digits d=%d ip" % d)
+
+
+def test_digitrev_misaligned_and_errors():
+    host = workloads.byte_pattern((1 << 14) * 4, seed=5)
+    want = oracle.digit_outofplace(host, 2, 4)
+    x = to_device(host, 4, pad_front=1)
+    br.bitrev_digitrev_inplace(x, 2, 14)
+    assert_bytes_equal(to_host_bytes(x), want, "misaligned")
+    with pytest.raises(br.BitrevError) as e:
+        br.bitrev_digitrev_inplace(torch.zeros(1 << 13, device="cuda"), 2)
+    assert e.value.status == br.ERROR_INVALID_VALUE
