@@ -77,6 +77,9 @@ class Oracle:
         L.oracle_digit_inplace.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_size_t]
         L.oracle_digit_inplace.restype = ctypes.c_int
+        L.oracle_evenodd.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.c_size_t]
+        L.oracle_evenodd.restype = ctypes.c_int
         self.lib = L
         self.path = path
 
@@ -157,6 +160,15 @@ class Oracle:
             raise ValueError("oracle_digit_inplace rejected its arguments")
         return a
 
+    def evenodd(self, a: np.ndarray, elem_size: int | None = None) -> np.ndarray:
+        """One even-odd split: evens first, then odds (Introduction, Stockham)."""
+        s, n = self._elems(a, elem_size)
+        k = _log2_exact(n)
+        out = np.empty_like(a)
+        if self.lib.oracle_evenodd(a.ctypes.data, out.ctypes.data, k, s) != 0:
+            raise ValueError("oracle_evenodd rejected its arguments")
+        return out
+
     def rev_table(self, k: int) -> np.ndarray:
         """rev_k(j) for every j, read off the in-place permutation of 0..n-1."""
         return self.inplace(np.arange(1 << k, dtype=np.int64))
@@ -208,3 +220,7 @@ def digit_outofplace(a, d, elem_size=None):
 
 def digit_inplace(a, d, elem_size=None):
     return default().digit_inplace(a, d, elem_size)
+
+
+def evenodd(a, elem_size=None):
+    return default().evenodd(a, elem_size)

@@ -188,4 +188,23 @@ int oracle_digit_inplace(void *data, int k, int d, size_t elem_size)
     return 0;
 }
 
+/* One even-odd split (Introduction, Stockham auto-sort): the even-indexed
+ * elements go to the first half in order, the odd-indexed ones to the second
+ * half -- the n/2 x 2 matrix transposition.  n = 2^k >= 2 out of place. */
+int oracle_evenodd(const void *src, void *dst, int k, size_t elem_size)
+{
+    const unsigned char *in = (const unsigned char *)src;
+    unsigned char *out = (unsigned char *)dst;
+    uint64_t n, half, j;
+    if (k < 1 || k > ORACLE_MAX_LOG2N || elem_size == 0 || !src || !dst)
+        return -1;
+    n = (uint64_t)1 << k;
+    half = n / 2;
+    for (j = 0; j < half; ++j) {
+        memcpy(out + j * elem_size, in + (2 * j) * elem_size, elem_size);
+        memcpy(out + (half + j) * elem_size, in + (2 * j + 1) * elem_size, elem_size);
+    }
+    return 0;
+}
+
 int oracle_version(void) { return 1; }

@@ -269,3 +269,29 @@ def pin_digit_reversal(o) -> None:
 
 
 ALL_PINS.append(pin_digit_reversal)
+
+
+def pin_evenodd_split(o) -> None:
+    """The even-odd split against the paper's 4 x 2 example and the
+    independent slicing form; applying it k times in nested halves is the
+    bit reversal (Introduction)."""
+    g = read_golden("evenodd_n8.txt")
+    a = np.arange(8, dtype=np.int64)
+    assert list(o.evenodd(a)) == [int(t) for t in g["output"].split()]
+    rng = np.random.default_rng(17)
+    for s in (1, 4, 8, 16):
+        for k in range(1, 12):
+            buf = rng.integers(0, 256, size=(1 << k) * s, dtype=np.uint8)
+            el = buf.reshape(-1, s)
+            want = np.concatenate([el[0::2], el[1::2]]).reshape(-1)
+            assert np.array_equal(o.evenodd(buf, s), want), (s, k)
+    for k in range(1, 11):
+        a = rng.integers(0, 2**62, size=1 << k, dtype=np.int64)
+        y = a.copy()
+        for level in range(k):
+            blocks = y.reshape(1 << level, -1)
+            y = np.concatenate([o.evenodd(np.ascontiguousarray(b)) for b in blocks])
+        assert np.array_equal(y, o.outofplace(a)), k
+
+
+ALL_PINS.append(pin_evenodd_split)

@@ -32,6 +32,8 @@ MUTANTS = [
     ("digits_reversed_bitwise", "r = (r << d) | ((i >> j) & mask);",
      "r = (r << d) | oracle_rev((i >> j) & mask, d);"),
     ("digit_dropped", "for (j = 0; j < k; j += d)", "for (j = d; j < k; j += d)"),
+    ("evenodd_swapped_halves", "memcpy(out + j * elem_size, in + (2 * j) * elem_size",
+     "memcpy(out + j * elem_size, in + (2 * j + 1) * elem_size"),
 ]
 
 
