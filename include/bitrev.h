@@ -120,6 +120,23 @@ bitrev_status_t bitrev_outofplace(const void* src, void* dst, int log2n, size_t 
 bitrev_status_t bitrev_rows(const void* src, void* dst, int log2n, int64_t rows,
                             size_t elem_size, void* stream);
 
+/* Strided rows: `rows` arrays of 2^log2n elements, array r starting at
+ * element r * src_stride of src and r * dst_stride of dst (strides in
+ * elements, >= 2^log2n).  src == dst (equal strides) is in place; otherwise
+ * the spans [src, src + ((rows-1) src_stride + 2^log2n) elem_size) and the
+ * same for dst must not overlap (BITREV_ERROR_ALIAS, a conservative check). */
+bitrev_status_t bitrev_rows_strided(const void* src, void* dst, int log2n, int64_t rows,
+                                    int64_t src_stride, int64_t dst_stride, size_t elem_size,
+                                    void* stream);
+
+/* One even-odd split per row, out of place (Introduction: the Stockham
+ * auto-sort's step, the n/2 x 2 matrix transposition): dst[j] = src[2j] and
+ * dst[n/2 + j] = src[2j + 1] for j < n/2, each of `rows` contiguous rows of
+ * n = 2^log2n >= 2 elements.  Applied to nested halves log2n times it gives
+ * the bit-reversed order.  src and dst must not overlap. */
+bitrev_status_t bitrev_evenodd(const void* src, void* dst, int log2n, int64_t rows,
+                               size_t elem_size, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched: many arrays of different lengths in one persistent launch        */
 /* ------------------------------------------------------------------------ */
@@ -148,6 +165,15 @@ size_t bitrev_batched_workspace_size(int64_t num_arrays);
 bitrev_status_t bitrev_batched(void* data, int64_t data_elems, const int64_t* offsets,
                                const int32_t* log2n, int64_t num_arrays, size_t elem_size,
                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Out of place: dst[offsets[a] + rev(i)] = src[offsets[a] + i] for every
+ * array, src and dst sharing one packed layout of data_elems elements (the
+ * two ranges must not overlap: BITREV_ERROR_ALIAS).  Arrays with n <= 2 are
+ * copied.  Otherwise as bitrev_batched (workspace, checks, rejection). */
+bitrev_status_t bitrev_batched_outofplace(const void* src, void* dst, int64_t data_elems,
+                                          const int64_t* offsets, const int32_t* log2n,
+                                          int64_t num_arrays, size_t elem_size, void* workspace,
+                                          size_t workspace_bytes, void* stream);
 
 /* Synchronous debug helper: waits for `stream`, then reads the rejection
  * count and first rejected array that the last bitrev_batched on this

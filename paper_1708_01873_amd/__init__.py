@@ -83,6 +83,9 @@ _SIGNATURES = {
     "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_dit_stages": ([_VP, _VP, _I, _I64, _I, _I, _I, _VP], _I),
     "bitrev_digitrev_inplace": ([_VP, _I, _I, _SZ, _VP], _I),
+    "bitrev_rows_strided": ([_VP, _VP, _I, _I64, _I64, _I64, _SZ, _VP], _I),
+    "bitrev_evenodd": ([_VP, _VP, _I, _I64, _SZ, _VP], _I),
+    "bitrev_batched_outofplace": ([_VP, _VP, _I64, _VP, _VP, _I64, _SZ, _VP, _SZ, _VP], _I),
     "bitrev_digitrev_outofplace": ([_VP, _VP, _I, _I, _SZ, _VP], _I),
     "bitrev_debug_digit_rev": ([ctypes.c_uint32, _I, _I], ctypes.c_uint32),
     "bitrev_debug_digit_pair_count": ([_I, _I], ctypes.c_uint64),
@@ -274,6 +277,64 @@ def bitrev_batched(data, offsets, log2n, workspace=None, *, tile_bits=0, grid_bl
     return data
 
 
+def bitrev_batched_outofplace(src, dst, offsets, log2n, workspace=None, *, stream=None):
+    """Out of place over the same packed layout: each array of ``src`` lands
+    bit-reversed at the same offsets of ``dst``."""
+    import torch
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2 or src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same element size and length")
+    if offsets.dtype != torch.int64 or log2n.dtype != torch.int32:
+        raise TypeError("offsets must be int64 and log2n int32")
+    op, _ = _tensor_args(offsets, "offsets")
+    lp, _ = _tensor_args(log2n, "log2n")
+    num = log2n.numel()
+    if offsets.numel() != num + 1:
+        raise ValueError("offsets must have num_arrays + 1 entries")
+    if workspace is None:
+        workspace = torch.empty(max(bitrev_batched_workspace_size(num), 1), dtype=torch.uint8,
+                                device=src.device)
+    wp, _ = _tensor_args(workspace, "workspace")
+    _check(_load().bitrev_batched_outofplace(sp, dp, src.numel(), op, lp, num, s, wp,
+                                             workspace.numel() * workspace.element_size(),
+                                             _stream(stream)), "bitrev_batched_outofplace")
+    return dst
+
+
+def bitrev_rows_strided(src, dst, log2n: int, rows: int, src_stride: int, dst_stride: int, *,
+                        stream=None):
+    """Rows of 2^log2n elements at element strides src_stride / dst_stride
+    from the start of each tensor's storage (``dst is src`` in place)."""
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2:
+        raise ValueError("src and dst must have the same element size")
+    need_s = (rows - 1) * src_stride + (1 << log2n) if rows else 0
+    need_d = (rows - 1) * dst_stride + (1 << log2n) if rows else 0
+    if src.numel() < need_s or dst.numel() < need_d:
+        raise ValueError("tensors are too small for the requested rows and strides")
+    _check(_load().bitrev_rows_strided(sp, dp, int(log2n), int(rows), int(src_stride),
+                                       int(dst_stride), s, _stream(stream)), "bitrev_rows_strided")
+    return dst
+
+
+def bitrev_evenodd(src, dst=None, *, stream=None):
+    """One even-odd (Stockham) split of every row (last dimension): evens
+    first, then odds.  Allocates ``dst`` when not given."""
+    if dst is None:
+        import torch
+        dst = torch.empty_like(src)
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2 or src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same element size and length")
+    k = _log2_exact(src.shape[-1])
+    _check(_load().bitrev_evenodd(sp, dp, k, src.numel() >> k, s, _stream(stream)),
+           "bitrev_evenodd")
+    return dst
+
+
 def bitrev_batched_errors(workspace, stream=None) -> tuple[int, int]:
     """(arrays rejected, first rejected or -1) of the last batched call on
     ``workspace``; waits for the stream."""
@@ -396,5 +457,6 @@ __all__ = [
     "bitrev_batched_workspace_size", "bitrev_batched_errors", "bitrev_copy",
     "bitrev_plan_query", "bitrev_load_tuning", "bitrev_tuning_format",
     "bitrev_inplace_recursive", "bitrev_transpose_inplace", "bitrev_dit_stages",
-    "bitrev_digitrev_inplace", "bitrev_digitrev_outofplace",
+    "bitrev_digitrev_inplace", "bitrev_digitrev_outofplace", "bitrev_batched_outofplace",
+    "bitrev_rows_strided", "bitrev_evenodd",
 ]

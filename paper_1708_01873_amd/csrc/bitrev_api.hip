@@ -354,15 +354,17 @@ bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo
 // ---------------------------------------------------------------------------
 // Launches.
 // ---------------------------------------------------------------------------
-hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void* dst, uint64_t n,
-                       const DeviceInfo& d, hipStream_t st) {
+hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void* dst,
+                       uint64_t src_stride, uint64_t dst_stride, const DeviceInfo& d,
+                       hipStream_t st) {
   TileLaunch a;
   a.src = src;
   a.dst = dst;
   a.m = p.m;
   a.items_per_seg = p.items_per_seg;
   a.total_items = p.total;
-  a.seg_elems = n;
+  a.seg_elems = src_stride;
+  a.dst_seg_elems = dst_stride;
   a.balanced = p.order == 2 ? 1 : 0;
   a.xcds = d.xcds;
   a.grid = p.grid;
@@ -377,13 +379,15 @@ hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void
 }
 
 hipError_t launch_wave(int s, const Plan& p, const void* src, void* dst, int k, int64_t rows,
-                       hipStream_t st) {
+                       uint64_t src_stride, uint64_t dst_stride, hipStream_t st) {
   WaveLaunch a;
   a.src = src;
   a.dst = dst;
   a.k = k;
   a.nseg = (uint64_t)rows;
   a.grid = p.grid;
+  a.src_stride = src_stride;
+  a.dst_stride = dst_stride;
   switch (s) {
     case 1: return launch_wave_s1(a, st);
     case 2: return launch_wave_s2(a, st);
@@ -406,8 +410,28 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 }
 
 // Common body of bitrev_inplace/outofplace/rows (+ _ex).
+// Largest power of two <= 16 dividing v (16 for v = 0).
+size_t align_of(uint64_t v) {
+  size_t al = 16;
+  while (al > 1 && (v & (al - 1))) al >>= 1;
+  return al;
+}
+
+// Bytes spanned by `rows` arrays of n elements placed `stride` elements apart.
+uint64_t footprint(uint64_t n, int64_t rows, uint64_t stride, size_t s) {
+  return rows <= 0 ? 0 : ((uint64_t)(rows - 1) * stride + n) * s;
+}
+
+bool ranges_overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bbytes && y < x + abytes;
+}
+
+// Common body of the plain, rows and strided entry points.  Strides are in
+// elements between consecutive arrays; 0 means 2^k (contiguous rows).
 bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_t s,
-                          const bitrev_config_t* cfg, void* stream, bool rows_call) {
+                          const bitrev_config_t* cfg, void* stream, uint64_t src_stride = 0,
+                          uint64_t dst_stride = 0) {
   // ---- validation: no HIP call before this block completes ----
   if (src == NULL || dst == NULL) return BITREV_ERROR_INVALID_VALUE;
   if (k < 0 || k > BITREV_MAX_LOG2N || !valid_elem_size(s) || rows < 0 || !valid_config(cfg))
@@ -415,26 +439,39 @@ bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_
   if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % s)
     return BITREV_ERROR_INVALID_VALUE;
   const uint64_t n = 1ull << k;
-  if (rows > 0 && (uint64_t)rows > (1ull << 62) / (n * s)) return BITREV_ERROR_INVALID_VALUE;
-  const size_t bytes = (size_t)(n * s * (uint64_t)rows);
+  if (src_stride == 0) src_stride = n;
+  if (dst_stride == 0) dst_stride = n;
+  if (src_stride < n || dst_stride < n || src_stride > (1ull << 50) || dst_stride > (1ull << 50))
+    return BITREV_ERROR_INVALID_VALUE;
+  if (rows > 0 && ((uint64_t)rows > (1ull << 62) / (src_stride * s) ||
+                   (uint64_t)rows > (1ull << 62) / (dst_stride * s)))
+    return BITREV_ERROR_INVALID_VALUE;
   const bool inplace = (src == dst);
-  if (!inplace && overlap(src, dst, bytes)) return BITREV_ERROR_ALIAS;
-  (void)rows_call;
+  if (inplace && src_stride != dst_stride) return BITREV_ERROR_INVALID_VALUE;
+  if (!inplace && ranges_overlap(src, footprint(n, rows, src_stride, s), dst,
+                                 footprint(n, rows, dst_stride, s)))
+    return BITREV_ERROR_ALIAS;
   if (rows == 0 || (inplace && k <= 1)) return BITREV_SUCCESS;
   // ---- plan and launch ----
   DeviceInfo d;
   bitrev_status_t st = device_info(&d, false);
   if (st != BITREV_SUCCESS) return st;
   Plan p;
-  st = plan_plain(inplace ? kModeInplace : kModeOutofplace, k, (int)s, rows, cfg,
-                  pointer_align(src, dst), d, true, &p);
+  size_t align = pointer_align(src, dst);
+  if (rows > 1) {
+    const size_t sa = align_of(src_stride * s), da = align_of(dst_stride * s);
+    if (sa < align) align = sa;
+    if (da < align) align = da;
+  }
+  st = plan_plain(inplace ? kModeInplace : kModeOutofplace, k, (int)s, rows, cfg, align, d, true,
+                  &p);
   if (st != BITREV_SUCCESS) return st;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (p.path == BITREV_PATH_WAVE) {
-    e = launch_wave((int)s, p, src, dst, k, rows, hs);
+    e = launch_wave((int)s, p, src, dst, k, rows, src_stride, dst_stride, hs);
   } else if (p.path == BITREV_PATH_TILE) {
-    e = launch_tile(inplace, (int)s, p, src, dst, n, d, hs);
+    e = launch_tile(inplace, (int)s, p, src, dst, src_stride, dst_stride, d, hs);
   }
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
 }
@@ -502,7 +539,7 @@ bitrev_status_t run_digit(const void* src, void* dst, int k, int d, size_t s, vo
   const uint64_t n = 1ull << k;
   const bool inplace = (src == dst);
   if (!inplace && overlap(src, dst, (size_t)(n * s))) return BITREV_ERROR_ALIAS;
-  if (d == 1) return run_plain(src, dst, k, 1, s, NULL, stream, false);
+  if (d == 1) return run_plain(src, dst, k, 1, s, NULL, stream);
   if (inplace && k <= d) return BITREV_SUCCESS;  // one digit: the identity
   // ---- plan and launch ----
   DeviceInfo dev;
@@ -594,7 +631,7 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
   const bool inplace = (src == dst);
   if (!inplace && overlap(src, dst, (size_t)(n * s * (uint64_t)rows))) return BITREV_ERROR_ALIAS;
   if (2 * stages > log2n || stages > max_tile_bits((int)s)) return BITREV_ERROR_NOT_SUPPORTED;
-  if (stages == 0) return run_plain(src, dst, log2n, rows, s, NULL, stream, true);
+  if (stages == 0) return run_plain(src, dst, log2n, rows, s, NULL, stream);
   if (rows == 0) return BITREV_SUCCESS;
   // ---- plan and launch ----
   DeviceInfo d;
@@ -636,41 +673,78 @@ bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size
   if (log2n <= 1) return BITREV_SUCCESS;
   const int h = log2n / 2;
   const int64_t rows = (int64_t)1 << h;
-  bitrev_status_t st = run_plain(data, data, h, rows, elem_size, NULL, stream, true);
+  bitrev_status_t st = run_plain(data, data, h, rows, elem_size, NULL, stream);
   if (st == BITREV_SUCCESS) st = run_transpose(data, h, elem_size, static_cast<hipStream_t>(stream));
-  if (st == BITREV_SUCCESS) st = run_plain(data, data, h, rows, elem_size, NULL, stream, true);
+  if (st == BITREV_SUCCESS) st = run_plain(data, data, h, rows, elem_size, NULL, stream);
   return st;
 }
 
 bitrev_status_t bitrev_inplace(void* data, int log2n, size_t elem_size, void* stream) {
-  return run_plain(data, data, log2n, 1, elem_size, NULL, stream, false);
+  return run_plain(data, data, log2n, 1, elem_size, NULL, stream);
 }
 
 bitrev_status_t bitrev_inplace_ex(void* data, int log2n, size_t elem_size,
                                   const bitrev_config_t* cfg, void* stream) {
-  return run_plain(data, data, log2n, 1, elem_size, cfg, stream, false);
+  return run_plain(data, data, log2n, 1, elem_size, cfg, stream);
 }
 
 bitrev_status_t bitrev_outofplace(const void* src, void* dst, int log2n, size_t elem_size,
                                   void* stream) {
   if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;
-  return run_plain(src, dst, log2n, 1, elem_size, NULL, stream, false);
+  return run_plain(src, dst, log2n, 1, elem_size, NULL, stream);
 }
 
 bitrev_status_t bitrev_outofplace_ex(const void* src, void* dst, int log2n, size_t elem_size,
                                      const bitrev_config_t* cfg, void* stream) {
   if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;
-  return run_plain(src, dst, log2n, 1, elem_size, cfg, stream, false);
+  return run_plain(src, dst, log2n, 1, elem_size, cfg, stream);
 }
 
 bitrev_status_t bitrev_rows(const void* src, void* dst, int log2n, int64_t rows,
                             size_t elem_size, void* stream) {
-  return run_plain(src, dst, log2n, rows, elem_size, NULL, stream, true);
+  return run_plain(src, dst, log2n, rows, elem_size, NULL, stream);
 }
 
 bitrev_status_t bitrev_rows_ex(const void* src, void* dst, int log2n, int64_t rows,
                                size_t elem_size, const bitrev_config_t* cfg, void* stream) {
-  return run_plain(src, dst, log2n, rows, elem_size, cfg, stream, true);
+  return run_plain(src, dst, log2n, rows, elem_size, cfg, stream);
+}
+
+bitrev_status_t bitrev_rows_strided(const void* src, void* dst, int log2n, int64_t rows,
+                                    int64_t src_stride, int64_t dst_stride, size_t elem_size,
+                                    void* stream) {
+  if (src_stride <= 0 || dst_stride <= 0) return BITREV_ERROR_INVALID_VALUE;
+  return run_plain(src, dst, log2n, rows, elem_size, NULL, stream, (uint64_t)src_stride,
+                   (uint64_t)dst_stride);
+}
+
+bitrev_status_t bitrev_evenodd(const void* src, void* dst, int log2n, int64_t rows,
+                               size_t elem_size, void* stream) {
+  if (src == NULL || dst == NULL || log2n < 1 || log2n > BITREV_MAX_LOG2N || rows < 0 ||
+      !valid_elem_size(elem_size) ||
+      (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % elem_size)
+    return BITREV_ERROR_INVALID_VALUE;
+  const uint64_t n = 1ull << log2n;
+  if (rows > 0 && (uint64_t)rows > (1ull << 62) / (n * elem_size)) return BITREV_ERROR_INVALID_VALUE;
+  const uint64_t bytes = n * elem_size * (uint64_t)rows;
+  if (ranges_overlap(src, bytes, dst, bytes)) return BITREV_ERROR_ALIAS;
+  if (rows == 0) return BITREV_SUCCESS;
+  DeviceInfo d;
+  bitrev_status_t st = device_info(&d, false);
+  if (st != BITREV_SUCCESS) return st;
+  const uint64_t pairs = (n / 2) * (uint64_t)rows;
+  const uint64_t want = (pairs + 255) / 256;
+  const uint32_t grid = (uint32_t)(want < (uint64_t)d.cus * 16 ? (want ? want : 1) : (uint64_t)d.cus * 16);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  switch (elem_size) {
+    case 1: e = launch_evenodd_s1(src, dst, log2n, (uint64_t)rows, grid, hs); break;
+    case 2: e = launch_evenodd_s2(src, dst, log2n, (uint64_t)rows, grid, hs); break;
+    case 4: e = launch_evenodd_s4(src, dst, log2n, (uint64_t)rows, grid, hs); break;
+    case 8: e = launch_evenodd_s8(src, dst, log2n, (uint64_t)rows, grid, hs); break;
+    default: e = launch_evenodd_s16(src, dst, log2n, (uint64_t)rows, grid, hs); break;
+  }
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
 }
 
 size_t bitrev_batched_workspace_size(int64_t num_arrays) {
@@ -679,10 +753,13 @@ size_t bitrev_batched_workspace_size(int64_t num_arrays) {
   return (raw + 255) / 256 * 256;
 }
 
-bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t* offsets,
-                                  const int32_t* log2n, int64_t num_arrays, size_t elem_size,
-                                  void* workspace, size_t workspace_bytes,
-                                  const bitrev_config_t* cfg, void* stream) {
+// Common body of the batched entry points; src != NULL means out of place
+// (src -> data, the same packed layout).
+static bitrev_status_t run_batched(const void* src, void* data, int64_t data_elems,
+                                   const int64_t* offsets, const int32_t* log2n,
+                                   int64_t num_arrays, size_t elem_size, void* workspace,
+                                   size_t workspace_bytes, const bitrev_config_t* cfg,
+                                   void* stream) {
   // ---- validation: no HIP call before this block completes ----
   if (num_arrays < 0 || num_arrays > (1ll << 40) || data_elems < 0 || !valid_elem_size(elem_size) ||
       !valid_config(cfg))
@@ -692,6 +769,12 @@ bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t*
   if (reinterpret_cast<uintptr_t>(data) % elem_size || reinterpret_cast<uintptr_t>(offsets) % 8 ||
       reinterpret_cast<uintptr_t>(log2n) % 4)
     return BITREV_ERROR_INVALID_VALUE;
+  if (src != NULL) {
+    if (reinterpret_cast<uintptr_t>(src) % elem_size) return BITREV_ERROR_INVALID_VALUE;
+    if ((uint64_t)data_elems > (1ull << 62) / elem_size) return BITREV_ERROR_INVALID_VALUE;
+    const uint64_t bytes = (uint64_t)data_elems * elem_size;
+    if (src == data || ranges_overlap(src, bytes, data, bytes)) return BITREV_ERROR_ALIAS;
+  }
   if (workspace == NULL || reinterpret_cast<uintptr_t>(workspace) % 8 ||
       workspace_bytes < bitrev_batched_workspace_size(num_arrays))
     return BITREV_ERROR_WORKSPACE;
@@ -703,6 +786,7 @@ bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t*
   st = plan_batched((int)elem_size, cfg, d, &p);
   if (st != BITREV_SUCCESS) return st;
   BatchedLaunch a;
+  a.src = src;
   a.data = data;
   a.offsets = offsets;
   a.log2n = log2n;
@@ -724,6 +808,23 @@ bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t*
     default: e = launch_batched_s16(a, hs); break;
   }
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t* offsets,
+                                  const int32_t* log2n, int64_t num_arrays, size_t elem_size,
+                                  void* workspace, size_t workspace_bytes,
+                                  const bitrev_config_t* cfg, void* stream) {
+  return run_batched(NULL, data, data_elems, offsets, log2n, num_arrays, elem_size, workspace,
+                     workspace_bytes, cfg, stream);
+}
+
+bitrev_status_t bitrev_batched_outofplace(const void* src, void* dst, int64_t data_elems,
+                                          const int64_t* offsets, const int32_t* log2n,
+                                          int64_t num_arrays, size_t elem_size, void* workspace,
+                                          size_t workspace_bytes, void* stream) {
+  if (src == NULL) return BITREV_ERROR_INVALID_VALUE;
+  return run_batched(src, dst, data_elems, offsets, log2n, num_arrays, elem_size, workspace,
+                     workspace_bytes, NULL, stream);
 }
 
 bitrev_status_t bitrev_batched(void* data, int64_t data_elems, const int64_t* offsets,

@@ -10,11 +10,12 @@ namespace {
 
 constexpr int kPrepThreads = 1024;
 
-// Work items of array a for the batched kernel at tile width b: 0 for n <= 2
-// (identity), 1 whole-array item when 2^k < 2^(2b), else one per tile pair.
+// Work items of array a for the batched kernel at tile width b: one
+// whole-array item when 2^k < 2^(2b) (none in place for n <= 2, the
+// identity), else one per tile pair (in place) or per tile (out of place).
 // Sets *bad and returns 0 when the array's metadata is inconsistent.
 __device__ int64_t batched_work(const int64_t* offsets, const int32_t* log2n, int64_t a,
-                                int64_t data_elems, int b, bool* bad) {
+                                int64_t data_elems, int b, bool oop, bool* bad) {
   const int k = log2n[a];
   const int64_t o0 = offsets[a];
   const int64_t o1 = offsets[a + 1];
@@ -24,9 +25,8 @@ __device__ int64_t batched_work(const int64_t* offsets, const int32_t* log2n, in
     *bad = true;
     return 0;
   }
-  if (k <= 1) return 0;
-  if (k < 2 * b) return 1;
-  return (int64_t)pair_count(k - 2 * b);
+  if (k < 2 * b) return (k <= 1 && !oop) ? 0 : 1;
+  return oop ? (int64_t)1 << (k - 2 * b) : (int64_t)pair_count(k - 2 * b);
 }
 
 // One workgroup: each thread takes a contiguous run of arrays, the block
@@ -36,7 +36,7 @@ __device__ int64_t batched_work(const int64_t* offsets, const int32_t* log2n, in
 __global__ __launch_bounds__(kPrepThreads) void k_batched_prep(const int64_t* offsets,
                                                                const int32_t* log2n, int64_t num,
                                                                int64_t data_elems, int b,
-                                                               int64_t* ws) {
+                                                               int oop, int64_t* ws) {
   __shared__ int64_t sum_sh[kPrepThreads];
   __shared__ int64_t bad_sh[kPrepThreads];
   __shared__ int64_t first_sh[kPrepThreads];
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_batched_prep(const int64_t* of
   int64_t sum = 0, nbad = 0, first = LLONG_MAX;
   for (int64_t a = a0; a < a1; ++a) {
     bool bad = false;
-    sum += batched_work(offsets, log2n, a, data_elems, b, &bad);
+    sum += batched_work(offsets, log2n, a, data_elems, b, oop != 0, &bad);
     if (bad) {
       ++nbad;
       if (first == LLONG_MAX) first = a;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_batched_prep(const int64_t* of
   for (int64_t a = a0; a < a1; ++a) {
     ws[2 + a] = run;
     bool bad = false;
-    run += batched_work(offsets, log2n, a, data_elems, b, &bad);
+    run += batched_work(offsets, log2n, a, data_elems, b, oop != 0, &bad);
   }
   if (t == kPrepThreads - 1) ws[2 + num] = sum_sh[t];
   if (t == 0) {
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_copy1(const uint8_t* __restrict__ src,
 
 hipError_t launch_batched_prep(const BatchedLaunch& a, hipStream_t st) {
   hipLaunchKernelGGL(k_batched_prep, dim3(1), dim3(kPrepThreads), 0, st, a.offsets, a.log2n, a.num,
-                     a.data_elems, a.b, a.ws);
+                     a.data_elems, a.b, a.src != nullptr ? 1 : 0, a.ws);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace(
 template <int S, int B, bool VEC>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
-    uint64_t seg_elems, int balanced, int xcds) {
+    uint64_t seg_elems, uint64_t dst_seg_elems, int balanced, int xcds) {
   typedef typename Bytes<S>::T E;
   constexpr int NT = tile_threads<S, B, VEC>();
   __shared__ E lds[TileShape<S, B, VEC>::TILE_E];
@@ -47,7 +47,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
     }
     const uint32_t y = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
     tile_outofplace<S, B, VEC, NT>(static_cast<const E*>(src) + seg * seg_elems,
-                                   static_cast<E*>(dst) + seg * seg_elems, m, y, lds);
+                                   static_cast<E*>(dst) + seg * dst_seg_elems, m, y, lds);
     __syncthreads();
   }
 }
@@ -118,7 +118,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace_pi
 template <int S, int B, bool VEC>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace_pipe(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
-    uint64_t seg_elems, int balanced, int xcds) {
+    uint64_t seg_elems, uint64_t dst_seg_elems, int balanced, int xcds) {
   typedef typename Bytes<S>::T E;
   typedef TileShape<S, B, VEC> Sh;
   constexpr int NT = tile_threads<S, B, VEC>();
@@ -130,7 +130,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
   if (item >= total_items) return;
   uint64_t local;
   const E* in = item_base<E>(const_cast<void*>(src), item, items_per_seg, total_items, seg_elems, &local);
-  E* out = static_cast<E*>(dst) + (in - static_cast<const E*>(src));
+  E* out = static_cast<E*>(dst) + (uint64_t)(in - static_cast<const E*>(src)) / seg_elems * dst_seg_elems;
   uint32_t y = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
   tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
   while (true) {
@@ -149,7 +149,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
     __syncthreads();
     item = next;
     in = nin;
-    out = static_cast<E*>(dst) + (in - static_cast<const E*>(src));
+    out = static_cast<E*>(dst) + (uint64_t)(in - static_cast<const E*>(src)) / seg_elems * dst_seg_elems;
     y = ny;
   }
 }
@@ -284,15 +284,37 @@ __global__ __launch_bounds__(256) void k_wave_digit(const void* src, void* dst, 
   }
 }
 
+// One even-odd (Stockham) split per row: evens to the first half, odds to
+// the second.  A thread moves one (even, odd) pair: the loads are contiguous
+// across the wavefront, and so is each of the two store streams.
+template <int S>
+__global__ __launch_bounds__(256) void k_evenodd(const void* src, void* dst, int k, uint64_t rows) {
+  typedef typename Bytes<S>::T E;
+  const uint64_t half = 1ull << (k - 1);
+  const uint64_t total = half * rows;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < total; p += stride) {
+    const uint64_t row = p >> (k - 1);
+    const uint64_t j = p & (half - 1);
+    const E* in = static_cast<const E*>(src) + (row << k) + 2 * j;
+    E* out = static_cast<E*>(dst) + (row << k);
+    const E a = in[0];
+    const E b = in[1];
+    out[j] = a;
+    out[half + j] = b;
+  }
+}
+
 // n = 2^k <= 64: one wavefront per array, four arrays per workgroup.
 template <int S>
-__global__ __launch_bounds__(256) void k_wave(const void* src, void* dst, int k, uint64_t nseg) {
+__global__ __launch_bounds__(256) void k_wave(const void* src, void* dst, int k, uint64_t nseg,
+                                              uint64_t src_stride, uint64_t dst_stride) {
   typedef typename Bytes<S>::T E;
   const int lane = (int)(threadIdx.x & 63u);
-  const uint64_t n = 1ull << k;
   for (uint64_t seg = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); seg < nseg;
        seg += (uint64_t)gridDim.x * 4) {
-    wave_array<S>(static_cast<const E*>(src) + seg * n, static_cast<E*>(dst) + seg * n, k, lane);
+    wave_array<S>(static_cast<const E*>(src) + seg * src_stride,
+                  static_cast<E*>(dst) + seg * dst_stride, k, lane);
   }
 }
 
@@ -346,6 +368,38 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched(
   }
 }
 
+// Batched, out of place: the same persistent walk, with one work item per
+// source tile (2^m per array) or per small array; dst holds the same layout.
+template <int S, int B>
+__global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched_oop(
+    const void* src, void* dst, const int64_t* offsets, const int32_t* log2n, int64_t num,
+    const int64_t* ws, int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  constexpr int NT = tile_threads<S, B, true>();
+  __shared__ E lds[2 * TileShape<S, B, true>::TILE_E];
+  const int64_t* scan = ws + 2;
+  const uint64_t total = (uint64_t)scan[num];
+  for (uint64_t item = xcd_block(xcds); item < total; item += gridDim.x) {
+    const int64_t a = find_array(scan, num, item);
+    const int k = log2n[a];
+    const E* in = static_cast<const E*>(src) + offsets[a];
+    E* out = static_cast<E*>(dst) + offsets[a];
+    if (k < 2 * B) {
+      small_array<S, NT>(in, out, k, lds);
+    } else {
+      const int m = k - 2 * B;
+      const uint32_t local = (uint32_t)(item - (uint64_t)scan[a]);
+      const uint32_t y = balanced ? spread_bits(local, m) : local;
+      if (((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0) {
+        tile_outofplace<S, B, true, NT>(in, out, m, y, lds);
+      } else {
+        tile_outofplace<S, B, false, NT>(in, out, m, y, lds);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int S, int B, bool VEC>
 hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
   if (a.pipelined) {
@@ -365,11 +419,11 @@ hipError_t run_tile_outofplace(const TileLaunch& a, hipStream_t st) {
   if (a.pipelined) {
     hipLaunchKernelGGL((k_tile_outofplace_pipe<S, B, VEC>), dim3(a.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
-                       a.total_items, a.seg_elems, a.balanced, a.xcds);
+                       a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced, a.xcds);
   } else {
     hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC>), dim3(a.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
-                       a.total_items, a.seg_elems, a.balanced, a.xcds);
+                       a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced, a.xcds);
   }
   return hipGetLastError();
 }
@@ -392,8 +446,14 @@ int occupancy_of(bool inplace, bool pipelined) {
 
 template <int S, int B>
 hipError_t run_batched(const BatchedLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_batched<S, B>), dim3(a.grid), dim3(tile_threads<S, B, true>()), 0, st,
-                     a.data, a.offsets, a.log2n, a.num, (const int64_t*)a.ws, a.balanced, a.xcds);
+  if (a.src != nullptr) {
+    hipLaunchKernelGGL((k_batched_oop<S, B>), dim3(a.grid), dim3(tile_threads<S, B, true>()), 0, st,
+                       a.src, a.data, a.offsets, a.log2n, a.num, (const int64_t*)a.ws, a.balanced,
+                       a.xcds);
+  } else {
+    hipLaunchKernelGGL((k_batched<S, B>), dim3(a.grid), dim3(tile_threads<S, B, true>()), 0, st,
+                       a.data, a.offsets, a.log2n, a.num, (const int64_t*)a.ws, a.balanced, a.xcds);
+  }
   return hipGetLastError();
 }
 
@@ -495,7 +555,8 @@ hipError_t BITREV_CAT(launch_tile_outofplace_s, BITREV_S)(int b, bool vec, const
 }
 
 hipError_t BITREV_CAT(launch_wave_s, BITREV_S)(const WaveLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_wave<BITREV_S>), dim3(a.grid), dim3(256), 0, st, a.src, a.dst, a.k, a.nseg);
+  hipLaunchKernelGGL((k_wave<BITREV_S>), dim3(a.grid), dim3(256), 0, st, a.src, a.dst, a.k, a.nseg,
+                     a.src_stride, a.dst_stride);
   return hipGetLastError();
 }
 
@@ -520,6 +581,12 @@ hipError_t BITREV_CAT(launch_digit_s, BITREV_S)(int d, int b, bool vec, const Ti
 hipError_t BITREV_CAT(launch_wave_digit_s, BITREV_S)(const WaveLaunch& a, int d, hipStream_t st) {
   hipLaunchKernelGGL((k_wave_digit<BITREV_S>), dim3(a.grid), dim3(256), 0, st, a.src, a.dst, a.k, d,
                      a.nseg);
+  return hipGetLastError();
+}
+
+hipError_t BITREV_CAT(launch_evenodd_s, BITREV_S)(const void* src, void* dst, int k, uint64_t rows,
+                                                  uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_evenodd<BITREV_S>), dim3(grid), dim3(256), 0, st, src, dst, k, rows);
   return hipGetLastError();
 }
 

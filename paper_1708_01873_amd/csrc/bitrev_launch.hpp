@@ -22,7 +22,8 @@ struct TileLaunch {
   int m;                    // middle bits: log2n - 2b
   uint64_t items_per_seg;   // work items per array
   uint64_t total_items;     // items_per_seg * number of arrays
-  uint64_t seg_elems;       // elements between consecutive arrays (2^log2n)
+  uint64_t seg_elems;       // elements between consecutive source arrays (>= 2^log2n)
+  uint64_t dst_seg_elems = 0; // between destination arrays (out of place)
   int balanced;             // work-item order: 0 natural, 1 balanced bit dealing
   int xcds;                 // number of XCDs the grid is dealt over
   uint32_t grid;            // workgroups (multiple of xcds)
@@ -35,6 +36,8 @@ struct WaveLaunch {
   int k;                    // log2n <= 6
   uint64_t nseg;            // number of arrays
   uint32_t grid;
+  uint64_t src_stride = 0;  // elements between consecutive arrays
+  uint64_t dst_stride = 0;
 };
 
 struct DitLaunch {
@@ -52,6 +55,7 @@ struct TransposeLaunch {
 };
 
 struct BatchedLaunch {
+  const void* src = nullptr;  // out of place: the source (data is the destination)
   void* data;
   const int64_t* offsets;
   const int32_t* log2n;
@@ -83,6 +87,8 @@ size_t tile_lds_bytes(int s, int b, bool inplace);
   hipError_t launch_digit_s##S(int d, int b, bool vec, const TileLaunch& a,          \
                                hipStream_t st);                                      \
   hipError_t launch_wave_digit_s##S(const WaveLaunch& a, int d, hipStream_t st);     \
+  hipError_t launch_evenodd_s##S(const void* src, void* dst, int k, uint64_t rows,   \
+                                 uint32_t grid, hipStream_t st);                     \
   int tile_threads_s##S(int b, bool vec);                                            \
   int tile_occupancy_s##S(int b, bool vec, bool inplace, bool pipelined);            \
   int batched_threads_s##S(int b);

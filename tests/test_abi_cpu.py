@@ -284,3 +284,21 @@ def test_digitrev_validation(L):
     assert L.bitrev_digitrev_inplace(FAKE, 24, 0, 8, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_digitrev_outofplace(FAKE, FAKE, 24, 2, 8, None) == br.ERROR_ALIAS
     assert L.bitrev_digitrev_inplace(FAKE, 3, 3, 8, None) == br.SUCCESS  # one digit
+
+
+def test_variant_entry_validation(L):
+    # strided rows: strides below the row length, unequal strides in place, overlap
+    assert L.bitrev_rows_strided(FAKE, FAKE + (1 << 20), 10, 4, 512, 1024, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_rows_strided(FAKE, FAKE, 10, 4, 2048, 1024, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_rows_strided(FAKE, FAKE + 4096, 10, 4, 2048, 2048, 4, None) == br.ERROR_ALIAS
+    assert L.bitrev_rows_strided(FAKE, FAKE + 4096, 10, 0, 2048, 2048, 4, None) == br.SUCCESS
+    # even-odd: n >= 2, out of place only
+    assert L.bitrev_evenodd(FAKE, FAKE + (1 << 20), 0, 1, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_evenodd(FAKE, FAKE, 4, 1, 4, None) == br.ERROR_ALIAS
+    assert L.bitrev_evenodd(FAKE, FAKE + 8, 4, 1, 4, None) == br.ERROR_ALIAS
+    assert L.bitrev_evenodd(FAKE, FAKE + 64, 4, 0, 4, None) == br.SUCCESS
+    # batched out of place: overlap, null source
+    ws = br.bitrev_batched_workspace_size(4)
+    assert L.bitrev_batched_outofplace(FAKE, FAKE + 64, 1024, FAKE, FAKE, 4, 8, FAKE, ws, None) == br.ERROR_ALIAS
+    assert L.bitrev_batched_outofplace(None, FAKE, 1024, FAKE, FAKE, 4, 8, FAKE, ws, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_batched_outofplace(FAKE, FAKE + (1 << 20), 1024, FAKE, FAKE, 4, 8, FAKE, 8, None) == br.ERROR_WORKSPACE
