@@ -34,17 +34,24 @@ def _k_of(n: int) -> int:
     return k
 
 
-def dit_stages(x: np.ndarray, stages: int, inverse: bool = False) -> np.ndarray:
-    """Closed form of bit reversal + the first `stages` DIT levels, complex128."""
-    x = np.asarray(x).astype(np.complex128).reshape(-1)
+def dit_stages(x: np.ndarray, stages: int, inverse: bool = False,
+               precision=np.complex128) -> np.ndarray:
+    """Closed form of bit reversal + the first `stages` DIT levels, computed in
+    `precision` (complex128 by default; np.clongdouble gives a reference
+    clearly more accurate than a complex128 computation under test)."""
+    x = np.asarray(x).astype(precision).reshape(-1)
     k = _k_of(x.size)
     L = int(stages)
     if not 0 <= L <= k:
         raise ValueError("stages must be in [0, log2 n]")
     q = 1 << L
-    sign = 1.0 if inverse else -1.0
+    real = np.longdouble if precision == np.clongdouble else np.float64
+    sign = real(1) if inverse else real(-1)
     u = np.arange(q)
-    W = np.exp(sign * 2j * np.pi * np.outer(u, u) / q)  # W[f, u]
+    # angle 2 pi (u f mod q) / q, reduced before scaling so it stays accurate
+    ang = (np.outer(u, u) % q).astype(real) * (real(2) * real(np.pi) if real is np.float64
+                                               else real(2) * np.arccos(real(-1))) / real(q)
+    W = (np.cos(ang) + 1j * sign * np.sin(ang)).astype(precision)  # W[f, u]
     cols = x.reshape(q, x.size // q)                    # cols[u, r] = x[r + 2^(k-L) u]
     F = W @ cols                                        # F[f, r]
     rev = _default().rev_table(k - L)                   # block J takes column rev(J)

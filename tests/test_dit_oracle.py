@@ -60,3 +60,16 @@ def test_higham_bound_values():
     b = dit.higham_bound(6, u32, u32)
     assert 1e-6 < b < 3e-6
     assert dit.higham_bound(0, u32, u32) == 0.0
+
+
+def test_extended_precision_reference_agrees():
+    """The extended-precision form agrees with the complex128 one to complex128
+    accuracy, and with numpy's FFT when L = k."""
+    for k in (4, 9, 12):
+        x = _rand(k, 300 + k)
+        for L in (0, 3, min(k, 6)):
+            a = dit.dit_stages(x, L, precision=np.clongdouble)
+            b = dit.dit_stages(x, L)
+            assert np.allclose(a.astype(np.complex128), b, atol=1e-12 * max(1.0, np.abs(b).max()))
+        full = dit.dit_stages(x, k, precision=np.clongdouble).astype(np.complex128)
+        assert np.allclose(full, np.fft.fft(x), atol=1e-9 * 2**k)
