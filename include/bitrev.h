@@ -72,6 +72,9 @@ typedef struct bitrev_config {
                     * workgroup loads its next tiles while storing the
                     * current ones; grid = resident workgroups unless
                     * grid_blocks is set) */
+  int xcd_remap;   /* 0 = choose, 1 = give each XCD a contiguous range of work
+                    * items (the dispatcher deals workgroups to the XCDs round
+                    * robin), 2 = leave the dispatch order as is */
 } bitrev_config_t;
 
 /* Which code path and geometry a call uses (bitrev_plan_query). */
@@ -91,6 +94,8 @@ typedef struct bitrev_plan {
   int order;            /* 1 natural, 2 balanced */
   int vector_access;    /* 1: 16-byte global accesses; 0: one element per access */
   int variant;          /* 1 one item per workgroup, 2 persistent pipelined */
+  int xcd_remap;        /* 1 contiguous ranges per XCD, 2 dispatch order */
+  int reserved;
   uint64_t work_items;  /* tile pairs (in place) or tiles (out of place), all rows */
   uint64_t lds_bytes;   /* LDS per workgroup */
 } bitrev_plan_t;

@@ -30,6 +30,7 @@ PATH_NONE, PATH_WAVE, PATH_TILE, PATH_BATCHED = 0, 1, 2, 3
 MODE_INPLACE, MODE_OUTOFPLACE, MODE_BATCHED = 0, 1, 2
 ORDER_DEFAULT, ORDER_NATURAL, ORDER_BALANCED = 0, 1, 2
 VARIANT_DEFAULT, VARIANT_ONE_ITEM, VARIANT_PIPELINED = 0, 1, 2
+XCD_DEFAULT, XCD_REMAP, XCD_DISPATCH_ORDER = 0, 1, 2
 
 
 class BitrevError(RuntimeError):
@@ -46,7 +47,7 @@ class BitrevError(RuntimeError):
 class Config(ctypes.Structure):
     """bitrev_config_t: zero fields mean "library choice"."""
     _fields_ = [("tile_bits", ctypes.c_int), ("grid_blocks", ctypes.c_int),
-                ("order", ctypes.c_int), ("variant", ctypes.c_int)]
+                ("order", ctypes.c_int), ("variant", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
 
 
 class Plan(ctypes.Structure):
@@ -54,11 +55,12 @@ class Plan(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int), ("tile_bits", ctypes.c_int), ("mid_bits", ctypes.c_int),
                 ("block_threads", ctypes.c_int), ("grid_blocks", ctypes.c_int),
                 ("order", ctypes.c_int), ("vector_access", ctypes.c_int),
-                ("variant", ctypes.c_int), ("work_items", ctypes.c_uint64),
+                ("variant", ctypes.c_int), ("xcd_remap", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("work_items", ctypes.c_uint64),
                 ("lds_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -138,11 +140,11 @@ def _check(status: int, where: str) -> None:
         raise BitrevError(status, where)
 
 
-def _config(tile_bits=0, grid_blocks=0, order=0, config=None, variant=0):
+def _config(tile_bits=0, grid_blocks=0, order=0, config=None, variant=0, xcd_remap=0):
     if config is not None:
         return config
-    if tile_bits or grid_blocks or order or variant:
-        return Config(int(tile_bits), int(grid_blocks), int(order), int(variant))
+    if tile_bits or grid_blocks or order or variant or xcd_remap:
+        return Config(int(tile_bits), int(grid_blocks), int(order), int(variant), int(xcd_remap))
     return None
 
 
@@ -174,12 +176,12 @@ def _log2_exact(n: int) -> int:
 
 
 def bitrev_inplace(data, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0, order=0,
-                   variant=0, config=None, stream=None):
+                   variant=0, xcd_remap=0, config=None, stream=None):
     """Replace ``data`` (2^log2n contiguous elements) by its bit-reversed
     permutation.  ``log2n`` defaults to log2(data.numel())."""
     ptr, s = _tensor_args(data, "data")
     k = _log2_exact(data.numel()) if log2n is None else int(log2n)
-    cfg = _config(tile_bits, grid_blocks, order, config, variant)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
     L = _load()
     if cfg is None:
         _check(L.bitrev_inplace(ptr, k, s, _stream(stream)), "bitrev_inplace")
@@ -190,7 +192,7 @@ def bitrev_inplace(data, log2n: Optional[int] = None, *, tile_bits=0, grid_block
 
 
 def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0,
-                      order=0, variant=0, config=None, stream=None):
+                      order=0, variant=0, xcd_remap=0, config=None, stream=None):
     """dst[rev(i)] = src[i]; allocates ``dst`` like ``src`` when not given."""
     if dst is None:
         import torch
@@ -200,7 +202,7 @@ def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0
     if s != s2 or src.numel() != dst.numel():
         raise ValueError("src and dst must have the same element size and length")
     k = _log2_exact(src.numel()) if log2n is None else int(log2n)
-    cfg = _config(tile_bits, grid_blocks, order, config, variant)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
     L = _load()
     if cfg is None:
         _check(L.bitrev_outofplace(sp, dp, k, s, _stream(stream)), "bitrev_outofplace")
@@ -211,7 +213,7 @@ def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0
 
 
 def bitrev_rows(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0,
-                order=0, variant=0, config=None, stream=None):
+                order=0, variant=0, xcd_remap=0, config=None, stream=None):
     """Permute every row of 2^log2n elements (default: the last dimension);
     ``dst is src`` works in place.  Allocates ``dst`` when not given."""
     if dst is None:
@@ -231,7 +233,7 @@ def bitrev_rows(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid
     if src.numel() % n:
         raise ValueError("%d elements are not a whole number of rows of %d" % (src.numel(), n))
     rows = src.numel() // n
-    cfg = _config(tile_bits, grid_blocks, order, config, variant)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
     L = _load()
     if cfg is None:
         _check(L.bitrev_rows(sp, dp, k, rows, s, _stream(stream)), "bitrev_rows")
@@ -246,7 +248,7 @@ def bitrev_batched_workspace_size(num_arrays: int) -> int:
 
 
 def bitrev_batched(data, offsets, log2n, workspace=None, *, tile_bits=0, grid_blocks=0, order=0,
-                   variant=0, config=None, stream=None):
+                   variant=0, xcd_remap=0, config=None, stream=None):
     """In place on every packed array [offsets[a], offsets[a+1]) of ``data``
     (lengths 2^log2n[a]).  ``offsets`` (int64, num+1) and ``log2n`` (int32,
     num) are device tensors; ``workspace`` is a device byte tensor of at least
@@ -266,7 +268,7 @@ def bitrev_batched(data, offsets, log2n, workspace=None, *, tile_bits=0, grid_bl
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=data.device)
     wp, _ = _tensor_args(workspace, "workspace")
     wbytes = workspace.numel() * workspace.element_size()
-    cfg = _config(tile_bits, grid_blocks, order, config, variant)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
     L = _load()
     if cfg is None:
         _check(L.bitrev_batched(dp, data.numel(), op, lp, num, s, wp, wbytes, _stream(stream)),
@@ -431,9 +433,9 @@ def bitrev_transpose_inplace(data, log2side: Optional[int] = None, *, stream=Non
 
 
 def bitrev_plan_query(log2n: int, elem_size: int, rows: int = 1, mode: int = MODE_INPLACE,
-                      *, tile_bits=0, grid_blocks=0, order=0, variant=0, config=None) -> dict:
+                      *, tile_bits=0, grid_blocks=0, order=0, variant=0, xcd_remap=0, config=None) -> dict:
     """The plan a call would use (no launch)."""
-    cfg = _config(tile_bits, grid_blocks, order, config, variant)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
     p = Plan()
     _check(_load().bitrev_plan_query(int(log2n), int(elem_size), int(rows), int(mode),
                                      ctypes.byref(cfg) if cfg is not None else None,

@@ -86,6 +86,7 @@ struct TuneEntry {
   int wg_per_cu = 0;
   int order = 0;
   int variant = 0;
+  int xcd_remap = 0;
 };
 
 std::mutex g_tune_mu;
@@ -96,7 +97,8 @@ const char kTuningFormat[] =
     "libbitrev tuning v1: one entry per line, '#' starts a comment; fields: mode "
     "(inplace|outofplace|batched) elem_size log2n(-1 = any) tile_bits(0 = default) "
     "wg_per_cu(0 = default) order(0 = default, 1 natural, 2 balanced) "
-    "variant(0 = default, 1 one item per workgroup, 2 persistent pipelined)";
+    "variant(0 = default, 1 one item per workgroup, 2 persistent pipelined) "
+    "xcd_remap(0 = default, 1 contiguous ranges per XCD, 2 dispatch order)";
 
 int mode_from_name(const char* s) {
   if (strcmp(s, "inplace") == 0) return 0;
@@ -122,15 +124,15 @@ bitrev_status_t load_tuning_file(const char* path) {
     char* hash = strchr(line, '#');
     if (hash) *hash = '\0';
     char mode[32];
-    int s, k, b, wg, order, variant;
+    int s, k, b, wg, order, variant, xcd;
     char extra[8];
-    const int got =
-        sscanf(line, "%31s %d %d %d %d %d %d %7s", mode, &s, &k, &b, &wg, &order, &variant, extra);
+    const int got = sscanf(line, "%31s %d %d %d %d %d %d %d %7s", mode, &s, &k, &b, &wg, &order,
+                           &variant, &xcd, extra);
     if (got <= 0) continue;  // blank or comment-only line
-    const int md = got >= 7 ? mode_from_name(mode) : -1;
-    if (got != 7 || md < 0 || !valid_elem_size((size_t)s) || k < -1 || k > BITREV_MAX_LOG2N ||
+    const int md = got >= 8 ? mode_from_name(mode) : -1;
+    if (got != 8 || md < 0 || !valid_elem_size((size_t)s) || k < -1 || k > BITREV_MAX_LOG2N ||
         b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 || order > 2 ||
-        variant < 0 || variant > 2) {
+        variant < 0 || variant > 2 || xcd < 0 || xcd > 2) {
       ok = false;
       break;
     }
@@ -139,6 +141,7 @@ bitrev_status_t load_tuning_file(const char* path) {
     t.wg_per_cu = wg;
     t.order = order;
     t.variant = variant;
+    t.xcd_remap = xcd;
     table[std::make_tuple(md, s, k)] = t;
   }
   fclose(f);
@@ -178,25 +181,26 @@ struct DefaultPlan {
   int b;
   int variant;
   int order;
+  int xcd_remap;
 };
 
 DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
   const bool small = array_bytes <= (512ull << 20);
   if (mode == 0) {  // in place
     switch (s) {
-      case 1: return {7, small ? 2 : 1, 2};
-      case 2: return {7, small ? 2 : 1, 2};
-      case 4: return {6, small ? 2 : 1, 2};
-      case 8: return small ? DefaultPlan{6, 2, 1} : DefaultPlan{6, 1, 2};
-      default: return small ? DefaultPlan{4, 2, 2} : DefaultPlan{4, 1, 1};
+      case 1: return {7, small ? 2 : 1, 2, 1};
+      case 2: return {7, small ? 2 : 1, 2, 1};
+      case 4: return {6, small ? 2 : 1, 2, 1};
+      case 8: return small ? DefaultPlan{6, 2, 1, 1} : DefaultPlan{6, 1, 2, 1};
+      default: return small ? DefaultPlan{4, 2, 2, 1} : DefaultPlan{4, 1, 1, 1};
     }
   }
   switch (s) {  // out of place (and batched tile width)
-    case 1: return {7, 1, 2};
-    case 2: return {7, 1, 2};
-    case 4: return {6, 1, 2};
-    case 8: return {5, 1, 2};
-    default: return {4, 1, 2};
+    case 1: return {7, 1, 2, 1};
+    case 2: return {7, 1, 2, 1};
+    case 4: return {6, 1, 2, 1};
+    case 8: return {5, 1, 2, 1};
+    default: return {4, 1, 2, 1};
   }
 }
 
@@ -227,7 +231,8 @@ int threads_of(int s, int b, bool vec) {
 bool valid_config(const bitrev_config_t* c) {
   if (!c) return true;
   return c->tile_bits >= 0 && c->tile_bits <= kMaxTileBits && c->grid_blocks >= 0 &&
-         c->order >= 0 && c->order <= 2 && c->variant >= 0 && c->variant <= 2;
+         c->order >= 0 && c->order <= 2 && c->variant >= 0 && c->variant <= 2 &&
+         c->xcd_remap >= 0 && c->xcd_remap <= 2;
 }
 
 uint32_t round_up(uint64_t v, uint32_t to) {
@@ -252,6 +257,7 @@ struct Plan {
   uint32_t grid = 0;
   int order = 2;
   int variant = 1;
+  int xcd_remap = 1;
   bool vec = true;
   uint64_t items_per_seg = 0;
   uint64_t total = 0;
@@ -268,6 +274,8 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
   const TuneEntry te = tune_lookup(mode, s, k);
   const DefaultPlan dp = default_plan(mode, s, ((uint64_t)s) << k);
   p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : dp.order);
+  p->xcd_remap = (cfg && cfg->xcd_remap) ? cfg->xcd_remap
+                                         : (te.xcd_remap ? te.xcd_remap : dp.xcd_remap);
   if (forced_b == 0 && k <= 6) {
     p->path = BITREV_PATH_WAVE;
     p->threads = 256;
@@ -340,6 +348,7 @@ bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo
   p->path = BITREV_PATH_BATCHED;
   p->b = b;
   p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : default_order());
+  p->xcd_remap = (cfg && cfg->xcd_remap) ? cfg->xcd_remap : (te.xcd_remap ? te.xcd_remap : 1);
   p->threads = threads_of(s, b, true);
   p->lds = tile_lds_bytes_for(s, b, 2);
   int per_cu = te.wg_per_cu > 0 ? te.wg_per_cu : resident_per_cu(p->threads, p->lds);
@@ -366,7 +375,7 @@ hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void
   a.seg_elems = src_stride;
   a.dst_seg_elems = dst_stride;
   a.balanced = p.order == 2 ? 1 : 0;
-  a.xcds = d.xcds;
+  a.xcds = p.xcd_remap == 2 ? 1 : d.xcds;
   a.grid = p.grid;
   a.pipelined = p.variant == 2 ? 1 : 0;
   switch (s) {
@@ -795,7 +804,7 @@ static bitrev_status_t run_batched(const void* src, void* data, int64_t data_ele
   a.ws = static_cast<int64_t*>(workspace);
   a.b = p.b;
   a.balanced = p.order == 2 ? 1 : 0;
-  a.xcds = d.xcds;
+  a.xcds = p.xcd_remap == 2 ? 1 : d.xcds;
   a.grid = p.grid;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   hipError_t e = launch_batched_prep(a, hs);
@@ -869,6 +878,7 @@ bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int
   plan->order = p.order;
   plan->vector_access = p.vec ? 1 : 0;
   plan->variant = p.path == BITREV_PATH_TILE ? p.variant : 0;
+  plan->xcd_remap = (p.path == BITREV_PATH_TILE || p.path == BITREV_PATH_BATCHED) ? p.xcd_remap : 0;
   plan->work_items = p.total;
   plan->lds_bytes = p.lds;
   return BITREV_SUCCESS;

@@ -43,11 +43,17 @@ class Candidate:
     order: int
     variant: int = 0
     wg_per_cu: int = 0
+    xcd_remap: int = 0
     ms: float = float("inf")
 
     def line(self, mode: int, elem_size: int, log2n: int) -> str:
-        return "%s %d %d %d %d %d %d" % (MODE_NAMES[mode], elem_size, log2n, self.tile_bits,
-                                         self.wg_per_cu, self.order, self.variant)
+        return "%s %d %d %d %d %d %d %d" % (MODE_NAMES[mode], elem_size, log2n, self.tile_bits,
+                                            self.wg_per_cu, self.order, self.variant,
+                                            self.xcd_remap)
+
+    def config(self) -> dict:
+        return dict(tile_bits=self.tile_bits, order=self.order, variant=self.variant,
+                    xcd_remap=self.xcd_remap)
 
 
 @dataclass
@@ -102,7 +108,8 @@ def plain_candidates(log2n: int, elem_size: int, mode: int) -> list[Candidate]:
             continue
         for order in (1, 2):
             for variant in (1, 2):
-                out.append(Candidate(b, order, variant))
+                for xcd in (1, 2):
+                    out.append(Candidate(b, order, variant, 0, xcd))
     return out
 
 
@@ -136,8 +143,7 @@ def tune_plain(log2n: int, elem_size: int, mode: int = MODE_INPLACE, *, rows: in
     ranking = []
     for c in candidates or plain_candidates(log2n, elem_size, mode):
         try:
-            c.ms = clock.median_ms(lambda: run(tile_bits=c.tile_bits, order=c.order,
-                                               variant=c.variant), reps)
+            c.ms = clock.median_ms(lambda: run(**c.config()), reps)
         except BitrevError:
             continue
         ranking.append(c)
@@ -149,7 +155,7 @@ def tune_plain(log2n: int, elem_size: int, mode: int = MODE_INPLACE, *, rows: in
 
 
 def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 2, 4, 8),
-                 tile_bits=None, orders=(1, 2)) -> TuneResult:
+                 tile_bits=None, orders=(1, 2), xcd_remaps=(1, 2)) -> TuneResult:
     """Time the batched launch on the caller's own batch (device tensors as
     for bitrev_batched) over tile widths, orders and workgroups per CU.  Each
     candidate runs an even number of times, so `data` ends unchanged."""
@@ -165,14 +171,16 @@ def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 2, 4, 8),
     for b in bs:
         for order in orders:
             for w in wg_per_cu:
-                c = Candidate(b, order, 0, w)
-                grid = w * cus if w else 0
-                try:
-                    c.ms = clock.median_ms(lambda: bitrev_batched(
-                        data, offsets, log2n, ws, tile_bits=b, order=order, grid_blocks=grid), reps)
-                except BitrevError:
-                    continue
-                ranking.append(c)
+                for xcd in xcd_remaps:
+                    c = Candidate(b, order, 0, w, xcd)
+                    grid = w * cus if w else 0
+                    try:
+                        c.ms = clock.median_ms(lambda: bitrev_batched(
+                            data, offsets, log2n, ws, tile_bits=b, order=order, grid_blocks=grid,
+                            xcd_remap=xcd), reps)
+                    except BitrevError:
+                        continue
+                    ranking.append(c)
     if not ranking:
         raise RuntimeError("no batched candidate ran")
     ranking.sort(key=lambda c: c.ms)
@@ -183,7 +191,8 @@ def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 2, 4, 8),
 def write_tuning(results: list[TuneResult], path: str, note: str = "") -> str:
     """Write the best plan of each result as a libbitrev tuning table."""
     props = torch.cuda.get_device_properties(0)
-    lines = ["# libbitrev tuning table (mode elem_size log2n tile_bits wg_per_cu order variant)",
+    lines = ["# libbitrev tuning table (mode elem_size log2n tile_bits wg_per_cu order variant "
+             "xcd_remap)",
              "# device: %s, %d compute units%s" % (props.name, props.multi_processor_count,
                                                    ("; " + note) if note else "")]
     for r in results:
@@ -238,9 +247,10 @@ def main() -> None:
         batch = (data, torch.from_numpy(offsets).cuda(), torch.from_numpy(l2).cuda())
     path = args.out or default_cache_path()
     for r in autotune(path, plain, batch, reps=args.reps):
-        print("%-10s s=%-2d k=%-3d best b=%d order=%d variant=%d wg/cu=%d  %.4f ms  (%.3fx built-in)"
-              % (MODE_NAMES[r.mode], r.elem_size, r.log2n, r.best.tile_bits, r.best.order,
-                 r.best.variant, r.best.wg_per_cu, r.best.ms, r.gain_over_default))
+        print("%-10s s=%-2d k=%-3d best b=%d order=%d variant=%d xcd=%d wg/cu=%d  %.4f ms  "
+              "(%.3fx built-in)" % (MODE_NAMES[r.mode], r.elem_size, r.log2n, r.best.tile_bits,
+                                    r.best.order, r.best.variant, r.best.xcd_remap,
+                                    r.best.wg_per_cu, r.best.ms, r.gain_over_default))
     print("wrote", path)
 
 

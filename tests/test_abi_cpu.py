@@ -89,7 +89,8 @@ def test_rows_validation(L):
 
 def test_config_validation(L):
     for cfg in (br.Config(8, 0, 0, 0), br.Config(-1, 0, 0, 0), br.Config(0, -5, 0, 0),
-                br.Config(0, 0, 3, 0), br.Config(0, 0, 0, 3), br.Config(0, 0, 0, -1)):
+                br.Config(0, 0, 3, 0), br.Config(0, 0, 0, 3), br.Config(0, 0, 0, -1),
+                br.Config(0, 0, 0, 0, 3)):
         assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
 
 
@@ -165,17 +166,19 @@ def test_plan_query_defaults(L):
 
 def test_tuning_file(L, tmp_path):
     good = tmp_path / "tune.txt"
-    good.write_text("# comment\n\ninplace 8 24 5 0 2 1   # trailing comment\n"
-                    "batched 8 -1 4 4 1 0\n")
+    good.write_text("# comment\n\ninplace 8 24 5 0 2 1 2   # trailing comment\n"
+                    "batched 8 -1 4 4 1 0 0\n")
     br.bitrev_load_tuning(str(good))
     try:
         p = br.bitrev_plan_query(24, 8)
-        assert (p["tile_bits"], p["order"], p["variant"]) == (5, 2, 1)
+        assert (p["tile_bits"], p["order"], p["variant"], p["xcd_remap"]) == (5, 2, 1, 2)
         assert br.bitrev_plan_query(22, 8)["tile_bits"] == 6  # no entry: default
         p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
         assert p["tile_bits"] == 4 and p["order"] == 1 and p["grid_blocks"] == 4 * 256
-        for bad in ("inplace 8 24 6 0 2\n", "sideways 8 24 6 0 2 0\n", "inplace 3 24 6 0 2 0\n",
-                    "inplace 8 24 9 0 2 0\n", "inplace 8 24 6 0 2 3\n", "inplace 8 24 6 0 2 0 7\n"):
+        for bad in ("inplace 8 24 6 0 2 0\n", "sideways 8 24 6 0 2 0 0\n",
+                    "inplace 3 24 6 0 2 0 0\n", "inplace 8 24 9 0 2 0 0\n",
+                    "inplace 8 24 6 0 2 3 0\n", "inplace 8 24 6 0 2 0 3\n",
+                    "inplace 8 24 6 0 2 0 0 7\n"):
             f = tmp_path / "bad.txt"
             f.write_text(bad)
             with pytest.raises(br.BitrevError):
