@@ -85,9 +85,9 @@ def gbs(nbytes: float, ms: float) -> float:
     return nbytes / (ms * 1e-3) / 1e9
 
 
-def read_traffic(bytes_per_launch: float):
+def read_traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+    it was taken on the same kernel and the current kernel source."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -96,6 +96,8 @@ def read_traffic(bytes_per_launch: float):
                     key, _, val = line.partition(":")
                     kv[key.strip()] = val.strip()
         if kv.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        if kv.get("kernel", "").replace(" ", "") != kernel.replace(" ", ""):
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -248,7 +250,9 @@ def main() -> int:
     copy_gbs = gbs(nbytes, copy_ms)
     log("copy %.1f GB/s (mean %.4f ms)" % (copy_gbs, copy_ms))
 
-    traffic = read_traffic(nbytes)
+    kernel = "%s<8,%d,true>" % ("k_tile_inplace_pipe" if plan["variant"] == 2 else "k_tile_inplace",
+                                plan["tile_bits"])
+    traffic = read_traffic(kernel)
     out = {
         "metric": "effective GB/s (2*n*elem_size/time) of the in-place bit-reversed permutation",
         "value": round(value, 2),
@@ -267,7 +271,8 @@ def main() -> int:
                                "in-place bitrev, complex64, n=2^24 (128 MiB), hot caches",
                    "log2n": k, "elem_size": s, "tile_bits": plan["tile_bits"],
                    "grid_blocks": plan["grid_blocks"], "block_threads": plan["block_threads"],
-                   "variant": plan["variant"], "order": plan["order"]},
+                   "variant": plan["variant"], "order": plan["order"],
+                   "xcd_remap": plan["xcd_remap"]},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "copy_GBps": round(copy_gbs, 2),
         "pct_of_copy": round(100.0 * value / copy_gbs, 2),
@@ -282,8 +287,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": round(value / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic, 1),
-            "kernel": "%s<8,%d,true>" % ("k_tile_inplace_pipe" if plan["variant"] == 2
-                                         else "k_tile_inplace", plan["tile_bits"]),
+            "kernel": kernel,
             "algorithmic_bytes_per_launch": nbytes,
         },
     }

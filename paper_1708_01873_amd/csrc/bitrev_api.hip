@@ -171,42 +171,47 @@ TuneEntry tune_lookup(int mode, int s, int k) {
 // ---------------------------------------------------------------------------
 enum { kModeInplace = 0, kModeOutofplace = 1, kModeBatched = 2 };
 
-// Built-in plan per (mode, element size, array bytes), from sweeps of every
-// compiled tile width, both work orders and both kernel variants on MI355X
-// (read-flushed caches, arrays of 64 MiB to 4 GiB).  Rows of 2^b * s >= 128
-// bytes keep every HBM access a run of whole 128-byte lines.  Arrays that
-// fit the 256 MiB Infinity Cache twice over favour the persistent pipelined
-// in-place kernel; larger ones the one-item-per-workgroup kernel.
+// Built-in plan per (mode, element size, array bytes), from sweeps of tile
+// width x work order x kernel variant x XCD renumbering on MI355X with the
+// caches evicted before each call (arrays of 16 MiB to 4 GiB); each entry is
+// the one closest to the best at every measured size.  Rows of 2^b * s >= 128
+// bytes keep every HBM access a run of whole 128-byte lines.  "small" arrays
+// (<= 512 MiB) interact with the 256 MiB Infinity Cache and favour different
+// choices than arrays far beyond it.
 struct DefaultPlan {
   int b;
-  int variant;
-  int order;
-  int xcd_remap;
+  int variant;   // 1 one item per workgroup, 2 persistent pipelined
+  int order;     // 1 natural, 2 balanced
+  int xcd_remap; // 1 contiguous ranges per XCD, 2 dispatch order
 };
 
 DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
   const bool small = array_bytes <= (512ull << 20);
   if (mode == 0) {  // in place
     switch (s) {
-      case 1: return {7, small ? 2 : 1, 2, 1};
-      case 2: return {7, small ? 2 : 1, 2, 1};
-      case 4: return {6, small ? 2 : 1, 2, 1};
-      case 8: return small ? DefaultPlan{6, 2, 1, 1} : DefaultPlan{6, 1, 2, 1};
-      default: return small ? DefaultPlan{4, 2, 2, 1} : DefaultPlan{4, 1, 1, 1};
+      case 1: return {7, 1, 2, small ? 2 : 1};
+      case 2: return {7, 1, 2, small ? 2 : 1};
+      case 4: return small ? DefaultPlan{6, 2, 2, 1} : DefaultPlan{6, 1, 2, 1};
+      case 8: return {6, 1, 2, small ? 2 : 1};
+      default: return small ? DefaultPlan{5, 1, 2, 2} : DefaultPlan{5, 1, 1, 2};
     }
   }
-  switch (s) {  // out of place (and batched tile width)
+  if (mode == 2) {  // batched (in place, persistent): complex64 measured on 4096 uneven arrays
+    switch (s) {
+      case 8: return {6, 0, 1, 1};
+      case 16: return {5, 0, 2, 1};
+      default: return {default_plan(0, s, 0).b, 0, 2, 1};
+    }
+  }
+  switch (s) {  // out of place
     case 1: return {7, 1, 2, 1};
     case 2: return {7, 1, 2, 1};
-    case 4: return {6, 1, 2, 1};
+    case 4: return small ? DefaultPlan{6, 1, 1, 2} : DefaultPlan{6, 1, 2, 1};
     case 8: return {5, 1, 2, 1};
-    default: return {4, 1, 2, 1};
+    default: return {5, 1, 2, 1};
   }
 }
 
-int default_tile_bits(int s) { return default_plan(1, s, 0).b; }
-
-int default_order() { return 2; }
 
 int occupancy_of(int s, int b, bool vec, bool inplace, bool pipelined) {
   switch (s) {
@@ -339,16 +344,17 @@ int resident_per_cu(int threads, size_t lds) {
 bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo& d, Plan* p) {
   *p = Plan();
   const TuneEntry te = tune_lookup(kModeBatched, s, -1);
-  int b = (cfg && cfg->tile_bits) ? cfg->tile_bits
-                                   : (te.tile_bits ? te.tile_bits : default_tile_bits(s));
+  const DefaultPlan dp = default_plan(kModeBatched, s, 0);
+  int b = (cfg && cfg->tile_bits) ? cfg->tile_bits : (te.tile_bits ? te.tile_bits : dp.b);
   if (!(cfg && cfg->tile_bits) && b > max_tile_bits(s)) b = max_tile_bits(s);
   if (b < kMinBatchedTileBits || b > max_tile_bits(s) ||
       tile_lds_bytes_for(s, b, 2) > d.lds_per_block)
     return BITREV_ERROR_NOT_SUPPORTED;
   p->path = BITREV_PATH_BATCHED;
   p->b = b;
-  p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : default_order());
-  p->xcd_remap = (cfg && cfg->xcd_remap) ? cfg->xcd_remap : (te.xcd_remap ? te.xcd_remap : 1);
+  p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : dp.order);
+  p->xcd_remap = (cfg && cfg->xcd_remap) ? cfg->xcd_remap
+                                         : (te.xcd_remap ? te.xcd_remap : dp.xcd_remap);
   p->threads = threads_of(s, b, true);
   p->lds = tile_lds_bytes_for(s, b, 2);
   int per_cu = te.wg_per_cu > 0 ? te.wg_per_cu : resident_per_cu(p->threads, p->lds);

@@ -131,14 +131,16 @@ def test_plan_query_defaults(L):
     assert p["work_items"] == (2**14 + 2**7) // 2
     assert p["grid_blocks"] % 8 == 0 and p["grid_blocks"] >= p["work_items"]
     # built-in plans measured on MI355X: complex64 2^24 in place -> b = 6,
-    # persistent pipelined; a 2 GiB array -> one item per workgroup
+    # balanced, one item per workgroup, dispatch order; 2 GiB -> XCD ranges
     p = br.bitrev_plan_query(24, 8)
-    assert (p["tile_bits"], p["variant"], p["order"]) == (6, 2, 1)
+    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 2, 2)
     p = br.bitrev_plan_query(28, 8)
-    assert (p["tile_bits"], p["variant"], p["order"]) == (6, 1, 2)
+    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 2, 1)
     p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
-    assert (p["tile_bits"], p["variant"], p["order"]) == (5, 1, 2)
+    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 1, 2, 1)
     assert p["work_items"] == 2**14
+    p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
+    assert (p["tile_bits"], p["order"], p["xcd_remap"]) == (6, 1, 1)
     p = br.bitrev_plan_query(5, 4)
     assert p["path"] == br.PATH_WAVE
     p = br.bitrev_plan_query(1, 4)
