@@ -55,8 +55,9 @@ class Timer:
         self.flush = flush
         self.scratch = None
         if flush:
-            self.scratch = torch.empty(FLUSH_BYTES // 4, dtype=torch.int32, device="cuda")
-            self.scratch.fill_(1)
+            # float32, so that sum() is one reduction kernel that only reads
+            # (an integer sum would first widen the buffer into a written copy)
+            self.scratch = torch.ones(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
 
     def _flush(self):
         if self.scratch is not None:

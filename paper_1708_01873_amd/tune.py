@@ -77,7 +77,8 @@ class _Clock:
     def __init__(self, device, flush_bytes: int):
         self.scratch = None
         if flush_bytes:
-            self.scratch = torch.ones(flush_bytes // 4, dtype=torch.int32, device=device)
+            # float32: its sum is a single read-only reduction kernel
+            self.scratch = torch.ones(flush_bytes // 4, dtype=torch.float32, device=device)
 
     def median_ms(self, fn, reps: int) -> float:
         fn()
