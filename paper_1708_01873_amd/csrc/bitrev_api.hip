@@ -173,8 +173,8 @@ enum { kModeInplace = 0, kModeOutofplace = 1, kModeBatched = 2 };
 
 // Built-in plan per (mode, element size, array bytes), from sweeps of tile
 // width x work order x kernel variant x XCD renumbering on MI355X with the
-// caches evicted before each call (arrays of 16 MiB to 4 GiB); each entry is
-// the one closest to the best at every measured size.  Rows of 2^b * s >= 128
+// caches evicted before each call (arrays of 8 MiB to 4 GiB); each entry is
+// the one closest to the best at every measured size of its class.  Rows of 2^b * s >= 128
 // bytes keep every HBM access a run of whole 128-byte lines.  "small" arrays
 // (<= 512 MiB) interact with the 256 MiB Infinity Cache and favour different
 // choices than arrays far beyond it.
@@ -187,6 +187,11 @@ struct DefaultPlan {
 
 DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
   const bool small = array_bytes <= (512ull << 20);
+  // up to 32 MiB the launch is short and the persistent pipelined kernel
+  // in dispatch order does best (complex64: within 2% of the best plan)
+  const bool tiny = array_bytes > 0 && array_bytes <= (32ull << 20);
+  if (tiny && mode == 0) return {s >= 16 ? 5 : (s == 8 ? 5 : (s == 4 ? 6 : 7)), 2, 1, 2};
+  if (tiny && mode == 1) return {s >= 8 ? 5 : (s == 4 ? 6 : 7), 2, 2, 2};
   if (mode == 0) {  // in place
     switch (s) {
       case 1: return {7, 1, 2, small ? 2 : 1};
