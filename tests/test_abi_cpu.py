@@ -138,6 +138,9 @@ def test_plan_query_defaults(L):
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 2, 1)
     p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 1, 2, 1)
+    # up to 32 MiB: persistent pipelined, dispatch order
+    p = br.bitrev_plan_query(22, 8)
+    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 2, 1, 2)
     assert p["work_items"] == 2**14
     p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
     assert (p["tile_bits"], p["order"], p["xcd_remap"]) == (6, 1, 1)
@@ -174,7 +177,7 @@ def test_tuning_file(L, tmp_path):
     try:
         p = br.bitrev_plan_query(24, 8)
         assert (p["tile_bits"], p["order"], p["variant"], p["xcd_remap"]) == (5, 2, 1, 2)
-        assert br.bitrev_plan_query(22, 8)["tile_bits"] == 6  # no entry: default
+        assert br.bitrev_plan_query(25, 8)["tile_bits"] == 6  # no entry: default
         p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
         assert p["tile_bits"] == 4 and p["order"] == 1 and p["grid_blocks"] == 4 * 256
         for bad in ("inplace 8 24 6 0 2 0\n", "sideways 8 24 6 0 2 0 0\n",
