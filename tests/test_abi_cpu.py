@@ -138,10 +138,10 @@ def test_plan_query_defaults(L):
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 2, 1)
     p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 1, 2, 1)
+    assert p["work_items"] == 2**14
     # up to 32 MiB: persistent pipelined, dispatch order
     p = br.bitrev_plan_query(22, 8)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 2, 1, 2)
-    assert p["work_items"] == 2**14
     p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
     assert (p["tile_bits"], p["order"], p["xcd_remap"]) == (6, 1, 1)
     p = br.bitrev_plan_query(5, 4)
