@@ -185,6 +185,56 @@ def batched_speedup(torch, br, reps: int):
     }
 
 
+def other_configs(torch, br, timer, reps: int) -> dict:
+    """The remaining configurations, timed like the headline (default plans,
+    caches evicted before each call)."""
+    from paper_1708_01873_amd import workloads
+    from paper_1708_01873_amd.autograd import BitRev
+    out = {}
+    med = statistics.median
+    # uint32, n = 2^10: launch-bound, reported in microseconds
+    x = torch.from_numpy(workloads.uint32_uniform(10, workloads.SEEDS["c1"]).view("int32")).cuda()
+    y = torch.empty_like(x)
+    out["uint32_2p10"] = {
+        "inplace_us": round(1e3 * med(timer.time(lambda: br.bitrev_inplace(x), reps)), 2),
+        "outofplace_us": round(1e3 * med(timer.time(lambda: br.bitrev_outofplace(x, y), reps)), 2)}
+    # the two 4 GiB arrays
+    for name, k, dt, seed in (("complex128_2p28", 28, torch.complex128, workloads.SEEDS["c3a"]),
+                              ("float32_2p30", 30, torch.float32, workloads.SEEDS["c3b"])):
+        x = workloads.device_normal(1 << k, seed, dt)
+        y = torch.empty_like(x)
+        nb = 2.0 * x.numel() * x.element_size()
+        r = max(2, reps // 4)
+        out[name] = {
+            "inplace_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_inplace(x), r))), 1),
+            "outofplace_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_outofplace(x, y), r))), 1),
+            "copy_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_copy(x, y), r))), 1)}
+        del x, y
+        torch.cuda.empty_cache()
+    # differentiation: 256 x 2^16 float32, forward and backward of BitRev
+    xh, wh = workloads.rows_float32(256, 16, workloads.SEEDS["c5"])
+    x = torch.from_numpy(xh).cuda().requires_grad_()
+    w = torch.from_numpy(wh).cuda()
+    nb = 2.0 * x.numel() * 4
+    fwd = timer.time(lambda: BitRev.apply(x), reps)
+    yv = BitRev.apply(x)
+    g = torch.ones_like(yv)
+    bwd = timer.time(lambda: torch.autograd.grad(yv, x, g, retain_graph=True), reps)
+    out["autograd_256x2p16_f32"] = {"forward_GBps": round(gbs(nb, med(fwd)), 1),
+                                    "backward_GBps": round(gbs(nb, med(bwd)), 1),
+                                    "forward_us": round(1e3 * med(fwd), 2),
+                                    "backward_us": round(1e3 * med(bwd), 2)}
+    del x, w, yv, g
+    # bit reversal fused with 6 radix-2 DIT levels, complex64 2^24, out of place
+    x = workloads.device_normal(1 << 24, workloads.SEEDS["c2"], torch.complex64)
+    y = torch.empty_like(x)
+    nb = 2.0 * x.numel() * 8
+    out["dit6_complex64_2p24"] = {
+        "GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_dit_stages(x, y, 6), reps))), 1),
+        "plain_outofplace_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_outofplace(x, y), reps))), 1)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +367,7 @@ def main() -> int:
             "GBps_effective": round(gbs(nbytes, rec_ms), 2),
             "ms": round(rec_ms, 5),
             "slowdown_vs_one_pass": round(rec_ms / mean_ms, 3)}
+        extras["other_configs"] = other_configs(torch, br, timer, args.steps)
         hot = Timer(torch, flush=False).time(step, args.steps)
         extras["hot_cache_inplace_GBps"] = round(gbs(nbytes, statistics.fmean(hot)), 2)
         log("extras: %s" % json.dumps(extras))

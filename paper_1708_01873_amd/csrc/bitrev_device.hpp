@@ -298,8 +298,10 @@ __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restri
   tile_scatter<S, B, VEC, NT, PT>(ra, lds);
   if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
   __syncthreads();
-  tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
+  // tile y first, then its partner: measured a few percent faster than the
+  // other order for arrays that fit the Infinity Cache
   if (!pal) tile_store<S, B, VEC, NT, PT>(base, rowstride, y, lds + Sh::TILE_E);
+  tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
 }
 
 // Out of place: tile y of `src` to tile rev_m(y) of `dst`.

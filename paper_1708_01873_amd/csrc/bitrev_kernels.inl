@@ -103,8 +103,8 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace_pi
       tile_load<S, B, VEC, NT, PT>(ra, nbase, rowstride, ny);
       if (nyr != ny) tile_load<S, B, VEC, NT, PT>(rb, nbase, rowstride, nyr);
     }
-    tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
     if (yr != y) tile_store<S, B, VEC, NT, PT>(base, rowstride, y, lds + Sh::TILE_E);
+    tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
     if (next >= total_items) break;
     __syncthreads();
     item = next;

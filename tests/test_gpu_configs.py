@@ -227,3 +227,29 @@ def test_autograd_gradcheck_and_double_backward():
     x = torch.randn(3, 32, dtype=torch.float64, device="cuda", requires_grad=True)
     assert torch.autograd.gradcheck(BitRev.apply, (x,))
     assert torch.autograd.gradgradcheck(BitRev.apply, (x,))
+
+
+@pytest.mark.parametrize("k,s", [(32, 1), (31, 2)])
+def test_more_than_2p32_elements_or_bytes(k, s):
+    """Element indices beyond 2^31 (k = 31, 32): 64-bit offsets throughout.
+    Sampled against the oracle's rev, then in place == out of place and the
+    involution on the whole array."""
+    n = 1 << k
+    dt = torch.uint8 if s == 1 else torch.int16
+    x = torch.empty(n, dtype=dt, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(k)
+    x.view(torch.uint8).random_(0, 256, generator=g)
+    y = br.bitrev_outofplace(x)
+    _sampled_check(x, y, k, seed=k)
+    keep = x.clone()
+    br.bitrev_inplace(x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    del y
+    _free_gpu()
+    br.bitrev_inplace(x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, keep)
+    del x, keep
+    _free_gpu()
