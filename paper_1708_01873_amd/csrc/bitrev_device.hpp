@@ -346,34 +346,76 @@ __device__ __forceinline__ void make_twiddles(typename ComplexOf<S>::T* tw) {
 
 // Levels 1 .. stages of the radix-2 DIT butterflies on `rows` staged rows:
 // for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b), w = exp(-+ 2 pi i / 2^s)
-// (sign + for the inverse).  A barrier ends each level.
+// (sign + for the inverse).  Two levels s, s+1 run in one pass over LDS as a
+// radix-4 step on the four elements t, t+h, t+2h, t+3h (h = 2^(s-1)) of a
+// block: the same butterflies, where level s+1's second twiddle
+// w_{s+1}^(t+h) = w_{s+1}^t * (-+ i) is applied exactly.  A barrier ends
+// each pass.
 template <int S, int B, int NT>
 __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, int stages,
                                          bool inverse, const typename ComplexOf<S>::T* tw) {
   typedef typename ComplexOf<S>::T F;
   constexpr int R = 1 << B;
-  constexpr int H = R / 2;
   constexpr int PE = TileShape<S, B, true>::PE;
   F* base = reinterpret_cast<F*>(lds);
-  for (int s = 1; s <= stages; ++s) {
-    const int half = 1 << (s - 1);
-    const int tstride = R >> s;
-    for (int beta = (int)threadIdx.x; beta < rows * H; beta += NT) {
-      const int row = beta / H;
-      const int tp = beta % H;
-      const int t = tp & (half - 1);
-      const int c0 = ((tp >> (s - 1)) << s) + t;
-      F* pa = base + 2 * (row * PE + c0);
-      F* pb = pa + 2 * half;
-      const F wr = tw[2 * t * tstride];
-      const F wi = inverse ? -tw[2 * t * tstride + 1] : tw[2 * t * tstride + 1];
-      const F ar = pa[0], ai = pa[1], br = pb[0], bi = pb[1];
-      const F tr = br * wr - bi * wi;
-      const F ti = br * wi + bi * wr;
-      pa[0] = ar + tr;
-      pa[1] = ai + ti;
-      pb[0] = ar - tr;
-      pb[1] = ai - ti;
+  const F sg = inverse ? (F)-1 : (F)1;  // conjugates the forward twiddles
+  int s = 1;
+  while (s <= stages) {
+    const int h = 1 << (s - 1);
+    if (s + 1 <= stages) {
+      // radix-4: items = rows x (R / 4); item -> (row, block, t)
+      const int q4 = R / 4;
+      for (int beta = (int)threadIdx.x; beta < rows * q4; beta += NT) {
+        const int row = beta / q4;
+        const int tp = beta % q4;
+        const int t = tp & (h - 1);
+        const int c0 = ((tp >> (s - 1)) << (s + 1)) + t;
+        F* p0 = base + 2 * (row * PE + c0);
+        F* p1 = p0 + 2 * h;
+        F* p2 = p0 + 4 * h;
+        F* p3 = p0 + 6 * h;
+        const F w1r = tw[2 * t * (R >> s)], w1i = sg * tw[2 * t * (R >> s) + 1];
+        const F w2r = tw[2 * t * (R >> (s + 1))], w2i = sg * tw[2 * t * (R >> (s + 1)) + 1];
+        const F a0r = p0[0], a0i = p0[1], a1r = p1[0], a1i = p1[1];
+        const F a2r = p2[0], a2i = p2[1], a3r = p3[0], a3i = p3[1];
+        // level s: (a0, a1) and (a2, a3) with w1
+        const F t1r = a1r * w1r - a1i * w1i, t1i = a1r * w1i + a1i * w1r;
+        const F t3r = a3r * w1r - a3i * w1i, t3i = a3r * w1i + a3i * w1r;
+        const F x0r = a0r + t1r, x0i = a0i + t1i, x1r = a0r - t1r, x1i = a0i - t1i;
+        const F x2r = a2r + t3r, x2i = a2i + t3i, x3r = a2r - t3r, x3i = a2i - t3i;
+        // level s+1: (x0, x2) with w2, (x1, x3) with w2 * (-+ i)
+        const F u2r = x2r * w2r - x2i * w2i, u2i = x2r * w2i + x2i * w2r;
+        const F v3r = x3r * w2r - x3i * w2i, v3i = x3r * w2i + x3i * w2r;
+        const F u3r = sg * v3i, u3i = -sg * v3r;  // v3 * (-i), or * (+i) inverse
+        p0[0] = x0r + u2r;
+        p0[1] = x0i + u2i;
+        p2[0] = x0r - u2r;
+        p2[1] = x0i - u2i;
+        p1[0] = x1r + u3r;
+        p1[1] = x1i + u3i;
+        p3[0] = x1r - u3r;
+        p3[1] = x1i - u3i;
+      }
+      s += 2;
+    } else {
+      const int H = R / 2;
+      for (int beta = (int)threadIdx.x; beta < rows * H; beta += NT) {
+        const int row = beta / H;
+        const int tp = beta % H;
+        const int t = tp & (h - 1);
+        const int c0 = ((tp >> (s - 1)) << s) + t;
+        F* pa = base + 2 * (row * PE + c0);
+        F* pb = pa + 2 * h;
+        const F wr = tw[2 * t * (R >> s)], wi = sg * tw[2 * t * (R >> s) + 1];
+        const F ar = pa[0], ai = pa[1], br = pb[0], bi = pb[1];
+        const F tr = br * wr - bi * wi;
+        const F ti = br * wi + bi * wr;
+        pa[0] = ar + tr;
+        pa[1] = ai + ti;
+        pb[0] = ar - tr;
+        pb[1] = ai - ti;
+      }
+      s += 1;
     }
     __syncthreads();
   }
