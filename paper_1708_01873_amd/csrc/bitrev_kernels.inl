@@ -205,16 +205,17 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
       __syncthreads();
-      dit_rows<S, B, NT>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw);
-      tile_store<S, B, VEC, NT, PT>(out, rowstride, yr, lds);
-      if (!pal) tile_store<S, B, VEC, NT, PT>(out, rowstride, y, lds + Sh::TILE_E);
+      // LDS rows [0, R) hold tile y's data bound for yr, rows [R, 2R) the reverse
+      const RowSink<E> sink{out, rowstride, yr, y, Sh::R};
+      dit_rows_store<S, B, NT>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw, sink);
     } else {
       const uint32_t y = spread_bits((uint32_t)local, m);
       tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       __syncthreads();
-      dit_rows<S, B, NT>(lds, Sh::R, stages, inverse != 0, tw);
-      tile_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
+      const uint32_t yr = rev_bits(y, m);
+      const RowSink<E> sink{out, rowstride, yr, yr, Sh::R};
+      dit_rows_store<S, B, NT>(lds, Sh::R, stages, inverse != 0, tw, sink);
     }
     __syncthreads();
   }
