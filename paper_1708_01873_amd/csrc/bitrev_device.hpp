@@ -354,33 +354,18 @@ __device__ __forceinline__ void make_twiddles(typename ComplexOf<S>::T* tw) {
   }
 }
 
-// Where the rows of a staged tile go in HBM: LDS row r < R belongs to tile
-// ya, row R + r to tile yb (in place, the pair's second tile).
-template <typename E> struct RowSink {
-  E* base;
-  uint64_t rowstride;
-  uint32_t ya, yb;
-  int rdim;  // R
-  __device__ __forceinline__ E* row(int r) const {
-    const uint32_t y = r < rdim ? ya : yb;
-    const int rr = r < rdim ? r : r - rdim;
-    return base + (uint64_t)rr * rowstride + (uint64_t)y * rdim;
-  }
-};
-
 // Levels 1 .. stages of the radix-2 DIT butterflies on `rows` staged rows:
 // for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b), w = exp(-+ 2 pi i / 2^s)
-// (sign + for the inverse).  Two levels s, s+1 run in one pass as a radix-4
-// step on the four elements t, t+h, t+2h, t+3h (h = 2^(s-1)) of a block: the
-// same butterflies, where level s+1's second twiddle w_{s+1}^(t+h) =
-// w_{s+1}^t * (-+ i) is applied exactly.  Every pass but the last reads and
-// writes LDS and ends with a barrier; the last pass writes its results
-// straight to HBM through `sink` (four or two element stores per thread,
-// each store instruction covering whole runs of a row).
+// (sign + for the inverse).  Two levels s, s+1 run in one pass over LDS as a
+// radix-4 step on the four elements t, t+h, t+2h, t+3h (h = 2^(s-1)) of a
+// block: the same butterflies, where level s+1's second twiddle
+// w_{s+1}^(t+h) = w_{s+1}^t * (-+ i) is applied exactly.  A barrier ends each
+// pass; the caller then writes the rows with tile_store (measured faster
+// than storing the last pass's results directly: 16-byte row stores
+// coalesce better than the butterflies' 8-byte element stores).
 template <int S, int B, int NT>
-__device__ __forceinline__ void dit_rows_store(typename Bytes<S>::T* lds, int rows, int stages,
-                                               bool inverse, const typename ComplexOf<S>::T* tw,
-                                               const RowSink<typename Bytes<S>::T>& sink) {
+__device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, int stages,
+                                         bool inverse, const typename ComplexOf<S>::T* tw) {
   typedef typename ComplexOf<S>::T F;
   constexpr int R = 1 << B;
   constexpr int PE = TileShape<S, B, true>::PE;
@@ -389,9 +374,7 @@ __device__ __forceinline__ void dit_rows_store(typename Bytes<S>::T* lds, int ro
   int s = 1;
   while (s <= stages) {
     const int h = 1 << (s - 1);
-    const bool radix4 = s + 1 <= stages;
-    const bool last = s + (radix4 ? 1 : 0) == stages;
-    if (radix4) {
+    if (s + 1 <= stages) {
       const int q4 = R / 4;
       for (int beta = (int)threadIdx.x; beta < rows * q4; beta += NT) {
         const int row = beta / q4;
@@ -415,22 +398,10 @@ __device__ __forceinline__ void dit_rows_store(typename Bytes<S>::T* lds, int ro
         const F u2r = x2r * w2r - x2i * w2i, u2i = x2r * w2i + x2i * w2r;
         const F v3r = x3r * w2r - x3i * w2i, v3i = x3r * w2i + x3i * w2r;
         const F u3r = sg * v3i, u3i = -sg * v3r;  // v3 * (-i), or * (+i) inverse
-        if (last) {
-          F* g = reinterpret_cast<F*>(sink.row(row)) + 2 * c0;
-          store_cplx(g, x0r + u2r, x0i + u2i);
-          store_cplx(g + 2 * h, x1r + u3r, x1i + u3i);
-          store_cplx(g + 4 * h, x0r - u2r, x0i - u2i);
-          store_cplx(g + 6 * h, x1r - u3r, x1i - u3i);
-        } else {
-          p0[0] = x0r + u2r;
-          p0[1] = x0i + u2i;
-          p2[0] = x0r - u2r;
-          p2[1] = x0i - u2i;
-          p1[0] = x1r + u3r;
-          p1[1] = x1i + u3i;
-          p3[0] = x1r - u3r;
-          p3[1] = x1i - u3i;
-        }
+        store_cplx(p0, x0r + u2r, x0i + u2i);
+        store_cplx(p2, x0r - u2r, x0i - u2i);
+        store_cplx(p1, x1r + u3r, x1i + u3i);
+        store_cplx(p3, x1r - u3r, x1i - u3i);
       }
       s += 2;
     } else {
@@ -446,20 +417,12 @@ __device__ __forceinline__ void dit_rows_store(typename Bytes<S>::T* lds, int ro
         const F ar = pa[0], ai = pa[1], br = pb[0], bi = pb[1];
         const F tr = br * wr - bi * wi;
         const F ti = br * wi + bi * wr;
-        if (last) {
-          F* g = reinterpret_cast<F*>(sink.row(row)) + 2 * c0;
-          store_cplx(g, ar + tr, ai + ti);
-          store_cplx(g + 2 * h, ar - tr, ai - ti);
-        } else {
-          pa[0] = ar + tr;
-          pa[1] = ai + ti;
-          pb[0] = ar - tr;
-          pb[1] = ai - ti;
-        }
+        store_cplx(pa, ar + tr, ai + ti);
+        store_cplx(pb, ar - tr, ai - ti);
       }
       s += 1;
     }
-    if (!last) __syncthreads();
+    __syncthreads();
   }
 }
 

@@ -173,7 +173,9 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_transpose_inpla
 #if BITREV_S == 8 || BITREV_S == 16
 // Bit reversal fused with the first `stages` radix-2 DIT levels (complex
 // elements), out of place (src != dst) or in place (src == dst, tile pairs).
-template <int S, int B, bool VEC>
+// Bit reversal fused with the first `stages` radix-2 DIT levels (complex
+// elements), in place (tile pairs) or out of place.
+template <int S, int B, bool VEC, bool INPLACE>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
     uint64_t seg_elems, int stages, int inverse, int xcds) {
@@ -182,10 +184,9 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
   typedef typename ComplexOf<S>::T F;
   constexpr int NT = tile_threads<S, B, VEC>();
   constexpr int PT = (Sh::CPT + NT - 1) / NT;
-  __shared__ E lds[2 * Sh::TILE_E];
+  __shared__ E lds[(INPLACE ? 2 : 1) * Sh::TILE_E];
   __shared__ F tw[(1 << B) > 1 ? (1 << B) : 2];
   make_twiddles<S, B, NT>(tw);
-  const bool inplace = (src == dst);
   const uint64_t rowstride = 1ull << (m + B);
   for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
     uint64_t seg = 0, local = item;
@@ -195,8 +196,9 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
     }
     const E* in = static_cast<const E*>(src) + seg * seg_elems;
     E* out = static_cast<E*>(dst) + seg * seg_elems;
-    Chunk<S, Sh::VB> ra[PT], rb[PT];
-    if (inplace) {
+    Chunk<S, Sh::VB> ra[PT];
+    if constexpr (INPLACE) {
+      Chunk<S, Sh::VB> rb[PT];
       const uint32_t y = pair_at(m, local, true);
       const uint32_t yr = rev_bits(y, m);
       const bool pal = (y == yr);
@@ -205,17 +207,16 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
       __syncthreads();
-      // LDS rows [0, R) hold tile y's data bound for yr, rows [R, 2R) the reverse
-      const RowSink<E> sink{out, rowstride, yr, y, Sh::R};
-      dit_rows_store<S, B, NT>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw, sink);
+      dit_rows<S, B, NT>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw);
+      if (!pal) tile_store<S, B, VEC, NT, PT>(out, rowstride, y, lds + Sh::TILE_E);
+      tile_store<S, B, VEC, NT, PT>(out, rowstride, yr, lds);
     } else {
       const uint32_t y = spread_bits((uint32_t)local, m);
       tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       __syncthreads();
-      const uint32_t yr = rev_bits(y, m);
-      const RowSink<E> sink{out, rowstride, yr, yr, Sh::R};
-      dit_rows_store<S, B, NT>(lds, Sh::R, stages, inverse != 0, tw, sink);
+      dit_rows<S, B, NT>(lds, Sh::R, stages, inverse != 0, tw);
+      tile_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
     }
     __syncthreads();
   }
@@ -223,9 +224,17 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
 
 template <int S, int B, bool VEC>
 hipError_t run_dit(const DitLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_tile_dit<S, B, VEC>), dim3(a.t.grid), dim3(tile_threads<S, B, VEC>()), 0,
-                     st, a.t.src, a.t.dst, a.t.m, a.t.items_per_seg, a.t.total_items,
-                     a.t.seg_elems, a.stages, a.inverse, a.t.xcds);
+  if (a.t.src == a.t.dst) {
+    hipLaunchKernelGGL((k_tile_dit<S, B, VEC, true>), dim3(a.t.grid),
+                       dim3(tile_threads<S, B, VEC>()), 0, st, a.t.src, a.t.dst, a.t.m,
+                       a.t.items_per_seg, a.t.total_items, a.t.seg_elems, a.stages, a.inverse,
+                       a.t.xcds);
+  } else {
+    hipLaunchKernelGGL((k_tile_dit<S, B, VEC, false>), dim3(a.t.grid),
+                       dim3(tile_threads<S, B, VEC>()), 0, st, a.t.src, a.t.dst, a.t.m,
+                       a.t.items_per_seg, a.t.total_items, a.t.seg_elems, a.stages, a.inverse,
+                       a.t.xcds);
+  }
   return hipGetLastError();
 }
 
