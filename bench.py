@@ -231,6 +231,8 @@ def other_configs(torch, br, timer, reps: int) -> dict:
     nb = 2.0 * x.numel() * 8
     out["dit6_complex64_2p24"] = {
         "GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_dit_stages(x, y, 6), reps))), 1),
+        "inplace_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_dit_stages(x, x, 6),
+                                                     reps))), 1),
         "plain_outofplace_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_outofplace(x, y), reps))), 1)}
     return out
 
@@ -368,8 +370,13 @@ def main() -> int:
             "ms": round(rec_ms, 5),
             "slowdown_vs_one_pass": round(rec_ms / mean_ms, 3)}
         extras["other_configs"] = other_configs(torch, br, timer, args.steps)
-        hot = Timer(torch, flush=False).time(step, args.steps)
+        hot_timer = Timer(torch, flush=False)
+        hot = hot_timer.time(step, args.steps)
+        hot_copy = hot_timer.time(lambda: br.bitrev_copy(x, y), args.steps)
         extras["hot_cache_inplace_GBps"] = round(gbs(nbytes, statistics.fmean(hot)), 2)
+        extras["hot_cache_copy_GBps"] = round(gbs(nbytes, statistics.fmean(hot_copy)), 2)
+        # the paper's unit: seconds per element (median of the timed steps)
+        extras["ns_per_element"] = round(1e6 * statistics.median(times) / n, 6)
         log("extras: %s" % json.dumps(extras))
         try:
             extras["batched"] = batched_speedup(torch, br, reps=5)

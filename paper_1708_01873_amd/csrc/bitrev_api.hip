@@ -346,7 +346,18 @@ int resident_per_cu(int threads, size_t lds) {
   return r < 1 ? 1 : r;
 }
 
-bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo& d, Plan* p) {
+int batched_occupancy_of(int s, int b, bool oop) {
+  switch (s) {
+    case 1: return batched_occupancy_s1(b, oop);
+    case 2: return batched_occupancy_s2(b, oop);
+    case 4: return batched_occupancy_s4(b, oop);
+    case 8: return batched_occupancy_s8(b, oop);
+    default: return batched_occupancy_s16(b, oop);
+  }
+}
+
+bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo& d,
+                             bool have_device, bool oop, Plan* p) {
   *p = Plan();
   const TuneEntry te = tune_lookup(kModeBatched, s, -1);
   const DefaultPlan dp = default_plan(kModeBatched, s, 0);
@@ -362,7 +373,13 @@ bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo
                                          : (te.xcd_remap ? te.xcd_remap : dp.xcd_remap);
   p->threads = threads_of(s, b, true);
   p->lds = tile_lds_bytes_for(s, b, 2);
-  int per_cu = te.wg_per_cu > 0 ? te.wg_per_cu : resident_per_cu(p->threads, p->lds);
+  int per_cu = te.wg_per_cu;
+  if (per_cu <= 0) {
+    // resident at once: LDS and threads, and the registers the kernel needs
+    per_cu = resident_per_cu(p->threads, p->lds);
+    const int occ = have_device ? batched_occupancy_of(s, b, oop) : 0;
+    if (occ > 0 && occ < per_cu) per_cu = occ;
+  }
   if (cfg && cfg->grid_blocks > 0) {
     p->grid = round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds);
   } else {
@@ -803,7 +820,7 @@ static bitrev_status_t run_batched(const void* src, void* data, int64_t data_ele
   bitrev_status_t st = device_info(&d, false);
   if (st != BITREV_SUCCESS) return st;
   Plan p;
-  st = plan_batched((int)elem_size, cfg, d, &p);
+  st = plan_batched((int)elem_size, cfg, d, true, src != NULL, &p);
   if (st != BITREV_SUCCESS) return st;
   BatchedLaunch a;
   a.src = src;
@@ -877,7 +894,7 @@ bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int
   bitrev_status_t st = device_info(&d, true, &have_device);
   if (st != BITREV_SUCCESS) return st;
   Plan p;
-  st = (mode == 2) ? plan_batched((int)elem_size, cfg, d, &p)
+  st = (mode == 2) ? plan_batched((int)elem_size, cfg, d, have_device, false, &p)
                    : plan_plain(mode, log2n, (int)elem_size, rows, cfg, 16, d, have_device, &p);
   if (st != BITREV_SUCCESS) return st;
   memset(plan, 0, sizeof *plan);

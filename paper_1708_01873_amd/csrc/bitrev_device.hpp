@@ -375,7 +375,7 @@ __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, in
   while (s <= stages) {
     const int h = 1 << (s - 1);
     if (s + 1 <= stages) {
-      const int q4 = R / 4;
+      const int q4 = R >= 4 ? R / 4 : 1;  // R = 2 never gets here (stages <= b)
       for (int beta = (int)threadIdx.x; beta < rows * q4; beta += NT) {
         const int row = beta / q4;
         const int tp = beta % q4;

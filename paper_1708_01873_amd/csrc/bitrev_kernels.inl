@@ -529,6 +529,23 @@ hipError_t dispatch_batched(const BatchedLaunch& a, hipStream_t st) {
   }
 }
 
+// Workgroups of a batched kernel that fit on one compute unit at once (its
+// registers can allow fewer than its LDS and thread count do).
+template <int S, int B = kMinBatchedTileBits>
+int batched_occupancy_for(int b, bool oop) {
+  if constexpr (B > max_tile_bits(S)) {
+    return 0;
+  } else {
+    if (b != B) return batched_occupancy_for<S, B + 1>(b, oop);
+    int n = 0;
+    const int nt = tile_threads<S, B, true>();
+    const hipError_t e =
+        oop ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched_oop<S, B>, nt, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<S, B>, nt, 0);
+    return e == hipSuccess ? n : 0;
+  }
+}
+
 template <int S, int B = 0>
 int occupancy_for(int b, bool vec, bool inplace, bool pipelined) {
   if constexpr (B > max_tile_bits(S)) {
@@ -608,6 +625,10 @@ int BITREV_CAT(tile_threads_s, BITREV_S)(int b, bool vec) { return threads_for<B
 
 int BITREV_CAT(tile_occupancy_s, BITREV_S)(int b, bool vec, bool inplace, bool pipelined) {
   return occupancy_for<BITREV_S>(b, vec, inplace, pipelined);
+}
+
+int BITREV_CAT(batched_occupancy_s, BITREV_S)(int b, bool oop) {
+  return batched_occupancy_for<BITREV_S>(b, oop);
 }
 
 int BITREV_CAT(batched_threads_s, BITREV_S)(int b) {

@@ -91,6 +91,7 @@ size_t tile_lds_bytes(int s, int b, bool inplace);
                                  uint32_t grid, hipStream_t st);                     \
   int tile_threads_s##S(int b, bool vec);                                            \
   int tile_occupancy_s##S(int b, bool vec, bool inplace, bool pipelined);            \
+  int batched_occupancy_s##S(int b, bool oop);                                     \
   int batched_threads_s##S(int b);
 
 BITREV_DECLARE_LAUNCHERS(1)

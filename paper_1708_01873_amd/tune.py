@@ -155,7 +155,7 @@ def tune_plain(log2n: int, elem_size: int, mode: int = MODE_INPLACE, *, rows: in
     return TuneResult(mode, elem_size, log2n, ranking[0], ranking, default_ms)
 
 
-def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 2, 4, 8),
+def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 1, 2, 4, 8),
                  tile_bits=None, orders=(1, 2), xcd_remaps=(1, 2)) -> TuneResult:
     """Time the batched launch on the caller's own batch (device tensors as
     for bitrev_batched) over tile widths, orders and workgroups per CU.  Each
