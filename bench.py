@@ -353,11 +353,11 @@ def main() -> int:
         extras["outofplace_GBps"] = round(gbs(nbytes, statistics.fmean(o)), 2)
         sweep = {}
         for b in (4, 5, 6):
-            for order in (1, 2):
+            for order in (1, 2, 3):
                 ti = timer.time(lambda: br.bitrev_inplace(x, k, tile_bits=b, order=order), args.steps)
                 to = timer.time(lambda: br.bitrev_outofplace(x, y, k, tile_bits=b, order=order),
                                 args.steps)
-                sweep["b%d_%s" % (b, "natural" if order == 1 else "balanced")] = {
+                sweep["b%d_%s" % (b, ("natural", "balanced", "grouped")[order - 1])] = {
                     "inplace_GBps": round(gbs(nbytes, statistics.fmean(ti)), 2),
                     "outofplace_GBps": round(gbs(nbytes, statistics.fmean(to)), 2)}
         extras["tile_sweep"] = sweep

@@ -66,7 +66,11 @@ typedef struct bitrev_config {
   int grid_blocks; /* workgroups launched; >0 makes the kernel loop over its
                     * work items with a grid stride (persistent); 0 = choose */
   int order;       /* work-item order: 0 = choose, 1 = natural, 2 = balanced
-                    * bit dealing (spreads tile rows over HBM channels) */
+                    * bit dealing (spreads tile rows over HBM channels),
+                    * 3 = grouped (in place: the pairs of 2^3 x 2^3 tiles that
+                    * share their middle bits run together, so both sides of
+                    * the swaps touch runs of neighbouring tiles; out of
+                    * place it is the balanced order) */
   int variant;     /* tile kernel: 0 = choose, 1 = one work item per
                     * workgroup, 2 = persistent and software-pipelined (each
                     * workgroup loads its next tiles while storing the
@@ -91,7 +95,7 @@ typedef struct bitrev_plan {
   int mid_bits;         /* m = log2n - 2b */
   int block_threads;    /* threads per workgroup */
   int grid_blocks;      /* workgroups launched */
-  int order;            /* 1 natural, 2 balanced */
+  int order;            /* 1 natural, 2 balanced, 3 grouped */
   int vector_access;    /* 1: 16-byte global accesses; 0: one element per access */
   int variant;          /* 1 one item per workgroup, 2 persistent pipelined */
   int xcd_remap;        /* 1 contiguous ranges per XCD, 2 dispatch order */
@@ -304,6 +308,10 @@ uint32_t bitrev_debug_rev(uint32_t v, int j);
 uint64_t bitrev_debug_pair_count(int m);
 /* The w-th such y in the kernels' enumeration order (balanced: 0 or 1). */
 uint32_t bitrev_debug_pair_at(int m, uint64_t w, int balanced);
+/* The w-th tile of the in-place kernels' order (the other tile of its pair
+ * is its reversal): order 1 natural, 2 balanced, 3 grouped -- see
+ * bitrev_config_t.order.  0xFFFFFFFF when m, w or order is out of range. */
+uint32_t bitrev_debug_inplace_pair_at(int m, uint64_t w, int order);
 /* The balanced bit dealing of a width-bit value. */
 uint32_t bitrev_debug_spread(uint32_t w, int width);
 /* The w-th tile pair (r <= c) of the square transpose, column by column. */

@@ -28,7 +28,7 @@ ERROR_NOT_SUPPORTED = 5
 
 PATH_NONE, PATH_WAVE, PATH_TILE, PATH_BATCHED = 0, 1, 2, 3
 MODE_INPLACE, MODE_OUTOFPLACE, MODE_BATCHED = 0, 1, 2
-ORDER_DEFAULT, ORDER_NATURAL, ORDER_BALANCED = 0, 1, 2
+ORDER_DEFAULT, ORDER_NATURAL, ORDER_BALANCED, ORDER_GROUPED = 0, 1, 2, 3
 VARIANT_DEFAULT, VARIANT_ONE_ITEM, VARIANT_PIPELINED = 0, 1, 2
 XCD_DEFAULT, XCD_REMAP, XCD_DISPATCH_ORDER = 0, 1, 2
 
@@ -99,6 +99,7 @@ _SIGNATURES = {
     "bitrev_debug_rev": ([ctypes.c_uint32, _I], ctypes.c_uint32),
     "bitrev_debug_pair_count": ([_I], ctypes.c_uint64),
     "bitrev_debug_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
+    "bitrev_debug_inplace_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
     "bitrev_debug_spread": ([ctypes.c_uint32, _I], ctypes.c_uint32),
     "bitrev_debug_tri_pair": ([ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32),
                                ctypes.POINTER(ctypes.c_uint32)], None),

@@ -109,6 +109,57 @@ __host__ __device__ __forceinline__ uint32_t pair_at(int m, uint64_t w, bool bal
   return y;
 }
 
+// Number of y in [0, 2^m) with y < rev_m(y): (2^m - 2^ceil(m/2)) / 2 (the
+// paper's swap count r, Methods, unrolling).  pair_at lists exactly these
+// for w < swap_pair_count(m), before any palindrome.
+__host__ __device__ __forceinline__ uint64_t swap_pair_count(int m) {
+  return ((1ull << m) - (1ull << ((m + 1) / 2))) >> 1;
+}
+
+// The t-th palindrome y = rev_m(y), 0 <= t < 2^ceil(m/2).
+__host__ __device__ __forceinline__ uint32_t palindrome_at(int m, uint32_t t) {
+  const int h = m >> 1;
+  if (m & 1) return ((t >> 1) << (h + 1)) | ((t & 1u) << h) | rev_bits(t >> 1, h);
+  return (t << h) | rev_bits(t, h);
+}
+
+// Grouped order of the in-place tile pairs (1 <= j, 2j <= m).  The m tile
+// bits are split as y = [t | c | s] (t and s of j bits), so that
+// rev_m(y) = [rev_j(s) | rev(c) | rev_j(t)].  A middle c < rev(c) owns the
+// 4^j pairs {[t|c|s], rev_m([t|c|s])} for all (t, s); a palindromic middle
+// owns the pairs of the 2j-bit values [t|s] under their own reversal.
+// Consecutive work items then cover 2^j neighbouring tiles on both sides of
+// the swap, where pair_at's outside-in order leaves a hole after every tile.
+// Returns one tile of the w-th pair (0 <= w < pair_count(m)); the other is
+// its reversal.
+__host__ __device__ __forceinline__ uint32_t group_pair_at(int m, int j, uint64_t w,
+                                                           bool balanced) {
+  const int mc = m - 2 * j;
+  const uint64_t per = 1ull << (2 * j);
+  const uint64_t r = swap_pair_count(mc);
+  uint32_t c, z;
+  if (w < r * per) {
+    c = pair_at(mc, w >> (2 * j), balanced);
+    z = (uint32_t)(w & (per - 1));
+  } else {
+    const uint64_t w2 = w - r * per;
+    const uint64_t pp = pair_count(2 * j);
+    const uint64_t g = w2 / pp;
+    c = palindrome_at(mc, (uint32_t)g);
+    z = pair_at(2 * j, w2 - g * pp, false);
+  }
+  const uint32_t t = z >> j, sb = z & ((1u << j) - 1u);
+  return (t << (mc + j)) | (c << j) | sb;
+}
+
+// The in-place kernels' order code: bit 0 balanced, bits 1.. the group
+// width j (0: pair_at's own order), at most m / 2 for an m-bit middle.
+__host__ __device__ __forceinline__ uint32_t inplace_pair_at(int m, uint64_t w, int order_code) {
+  const int j = (order_code >> 1) < (m >> 1) ? (order_code >> 1) : (m >> 1);
+  const bool bal = (order_code & 1) != 0;
+  return j ? group_pair_at(m, j, w, bal) : pair_at(m, w, bal);
+}
+
 // ---------------------------------------------------------------------------
 // Digit reversal for radix-2^D FFTs: the order of the D-bit digits of an
 // index is reversed, each digit keeping its own bits.  D = 1 is rev_bits.

@@ -25,7 +25,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace(
       seg = item / items_per_seg;
       local = item - seg * items_per_seg;
     }
-    const uint32_t y = pair_at(m, local, balanced != 0);
+    const uint32_t y = inplace_pair_at(m, local, balanced);
     tile_pair_inplace<S, B, VEC, NT>(static_cast<E*>(data) + seg * seg_elems, m, y, lds);
     __syncthreads();
   }
@@ -85,7 +85,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace_pi
   if (item >= total_items) return;
   uint64_t local;
   E* base = item_base<E>(data, item, items_per_seg, total_items, seg_elems, &local);
-  uint32_t y = pair_at(m, local, balanced != 0);
+  uint32_t y = inplace_pair_at(m, local, balanced);
   uint32_t yr = rev_bits(y, m);
   tile_load<S, B, VEC, NT, PT>(ra, base, rowstride, y);
   if (yr != y) tile_load<S, B, VEC, NT, PT>(rb, base, rowstride, yr);
@@ -98,7 +98,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace_pi
     uint32_t ny = 0, nyr = 0;
     if (next < total_items) {
       nbase = item_base<E>(data, next, items_per_seg, total_items, seg_elems, &local);
-      ny = pair_at(m, local, balanced != 0);
+      ny = inplace_pair_at(m, local, balanced);
       nyr = rev_bits(ny, m);
       tile_load<S, B, VEC, NT, PT>(ra, nbase, rowstride, ny);
       if (nyr != ny) tile_load<S, B, VEC, NT, PT>(rb, nbase, rowstride, nyr);
@@ -178,7 +178,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_transpose_inpla
 template <int S, int B, bool VEC, bool INPLACE>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
-    uint64_t seg_elems, int stages, int inverse, int xcds) {
+    uint64_t seg_elems, int stages, int inverse, int order, int xcds) {
   typedef typename Bytes<S>::T E;
   typedef TileShape<S, B, VEC> Sh;
   typedef typename ComplexOf<S>::T F;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
     Chunk<S, Sh::VB> ra[PT];
     if constexpr (INPLACE) {
       Chunk<S, Sh::VB> rb[PT];
-      const uint32_t y = pair_at(m, local, true);
+      const uint32_t y = inplace_pair_at(m, local, order);
       const uint32_t yr = rev_bits(y, m);
       const bool pal = (y == yr);
       tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
@@ -228,12 +228,12 @@ hipError_t run_dit(const DitLaunch& a, hipStream_t st) {
     hipLaunchKernelGGL((k_tile_dit<S, B, VEC, true>), dim3(a.t.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.t.src, a.t.dst, a.t.m,
                        a.t.items_per_seg, a.t.total_items, a.t.seg_elems, a.stages, a.inverse,
-                       a.t.xcds);
+                       a.t.balanced, a.t.xcds);
   } else {
     hipLaunchKernelGGL((k_tile_dit<S, B, VEC, false>), dim3(a.t.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.t.src, a.t.dst, a.t.m,
                        a.t.items_per_seg, a.t.total_items, a.t.seg_elems, a.stages, a.inverse,
-                       a.t.xcds);
+                       a.t.balanced, a.t.xcds);
   }
   return hipGetLastError();
 }
@@ -367,7 +367,7 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched(
       small_array<S, NT>(base, base, k, lds);
     } else {
       const int m = k - 2 * B;
-      const uint32_t y = pair_at(m, item - (uint64_t)scan[a], balanced != 0);
+      const uint32_t y = inplace_pair_at(m, item - (uint64_t)scan[a], balanced);
       if ((reinterpret_cast<uintptr_t>(base) & 15u) == 0) {
         tile_pair_inplace<S, B, true, NT>(base, m, y, lds);
       } else {

@@ -89,7 +89,7 @@ def test_rows_validation(L):
 
 def test_config_validation(L):
     for cfg in (br.Config(8, 0, 0, 0), br.Config(-1, 0, 0, 0), br.Config(0, -5, 0, 0),
-                br.Config(0, 0, 3, 0), br.Config(0, 0, 0, 3), br.Config(0, 0, 0, -1),
+                br.Config(0, 0, 4, 0), br.Config(0, 0, 0, 3), br.Config(0, 0, 0, -1),
                 br.Config(0, 0, 0, 0, 3)):
         assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
 
@@ -130,12 +130,12 @@ def test_plan_query_defaults(L):
     assert p["path"] == br.PATH_TILE and p["tile_bits"] == 5 and p["mid_bits"] == 14
     assert p["work_items"] == (2**14 + 2**7) // 2
     assert p["grid_blocks"] % 8 == 0 and p["grid_blocks"] >= p["work_items"]
-    # built-in plans measured on MI355X: complex64 2^24 in place -> b = 6,
-    # balanced, one item per workgroup, dispatch order; 2 GiB -> XCD ranges
+    # built-in plans measured on MI355X: complex64 in place -> b = 6,
+    # grouped order, one item per workgroup, dispatch order
     p = br.bitrev_plan_query(24, 8)
-    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 2, 2)
+    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
     p = br.bitrev_plan_query(28, 8)
-    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 2, 1)
+    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
     p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 1, 2, 1)
     assert p["work_items"] == 2**14
@@ -220,6 +220,34 @@ def test_pair_enumeration_is_a_bijection(L, m, balanced):
     assert np.all(ys <= revs[ys])
     assert count == int(np.count_nonzero(np.arange(2**m) <= revs))
     assert L.bitrev_debug_pair_at(m, count, balanced) == 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("m", list(range(0, 15)))
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_inplace_order_covers_every_pair_once(L, m, order):
+    """Every order of the in-place work items (natural, balanced, grouped)
+    names each tile pair {y, rev_m(y)} exactly once."""
+    count = L.bitrev_debug_pair_count(m)
+    revs = oracle.rev_table(m)
+    ys = np.array([L.bitrev_debug_inplace_pair_at(m, w, order) for w in range(count)],
+                  dtype=np.int64)
+    assert np.all(ys < 2**m)
+    lo = np.minimum(ys, revs[ys])
+    assert len(np.unique(lo)) == count
+    assert L.bitrev_debug_inplace_pair_at(m, count, order) == 0xFFFFFFFF
+
+
+def test_grouped_order_runs_of_neighbouring_tiles(L):
+    """The grouped order's first 4^j items (j = 3) touch 2^j runs of 2^j
+    neighbouring tiles on each side of the swap."""
+    m = 12
+    ys = np.array([L.bitrev_debug_inplace_pair_at(m, w, 3) for w in range(64)], dtype=np.int64)
+    rs = oracle.rev_table(m)[ys]
+    for side in (ys, rs):
+        starts = np.unique(side >> 3)
+        assert len(starts) == 8
+        assert np.all(np.sort(side).reshape(8, 8) - (np.sort(side).reshape(8, 8)[:, :1])
+                      == np.arange(8))
 
 
 @pytest.mark.parametrize("m", [20, 27, 32])
