@@ -312,6 +312,9 @@ uint32_t bitrev_debug_pair_at(int m, uint64_t w, int balanced);
  * is its reversal): order 1 natural, 2 balanced, 3 grouped -- see
  * bitrev_config_t.order.  0xFFFFFFFF when m, w or order is out of range. */
 uint32_t bitrev_debug_inplace_pair_at(int m, uint64_t w, int order);
+/* The w-th source tile of the out-of-place kernels' order (1 natural,
+ * 2 balanced, 3 grouped); 0xFFFFFFFF when m, w or order is out of range. */
+uint32_t bitrev_debug_oop_tile_at(int m, uint32_t w, int order);
 /* The balanced bit dealing of a width-bit value. */
 uint32_t bitrev_debug_spread(uint32_t w, int width);
 /* The w-th tile pair (r <= c) of the square transpose, column by column. */

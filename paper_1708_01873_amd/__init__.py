@@ -100,6 +100,7 @@ _SIGNATURES = {
     "bitrev_debug_pair_count": ([_I], ctypes.c_uint64),
     "bitrev_debug_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
     "bitrev_debug_inplace_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
+    "bitrev_debug_oop_tile_at": ([_I, ctypes.c_uint32, _I], ctypes.c_uint32),
     "bitrev_debug_spread": ([ctypes.c_uint32, _I], ctypes.c_uint32),
     "bitrev_debug_tri_pair": ([ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32),
                                ctypes.POINTER(ctypes.c_uint32)], None),

@@ -160,6 +160,20 @@ __host__ __device__ __forceinline__ uint32_t inplace_pair_at(int m, uint64_t w, 
   return j ? group_pair_at(m, j, w, bal) : pair_at(m, w, bal);
 }
 
+// The w-th source tile of the out-of-place kernels for an order code (see
+// inplace_pair_at).  Grouped: y = [t | c | s] with (s, t) the low 2j bits of
+// w, s fastest, and the middle c dealt by spread_bits from the rest, so that
+// each run of 4^j items covers 2^j neighbouring tiles on both sides.
+__host__ __device__ __forceinline__ uint32_t oop_tile_at(int m, uint32_t w, int order_code) {
+  const int j = (order_code >> 1) < (m >> 1) ? (order_code >> 1) : (m >> 1);
+  if (j == 0) return (order_code & 1) ? spread_bits(w, m) : w;
+  const int mc = m - 2 * j;
+  const uint32_t s = w & ((1u << j) - 1u);
+  const uint32_t t = (w >> j) & ((1u << j) - 1u);
+  const uint32_t c = spread_bits(w >> (2 * j), mc);
+  return (t << (mc + j)) | (c << j) | s;
+}
+
 // ---------------------------------------------------------------------------
 // Digit reversal for radix-2^D FFTs: the order of the D-bit digits of an
 // index is reversed, each digit keeping its own bits.  D = 1 is rev_bits.

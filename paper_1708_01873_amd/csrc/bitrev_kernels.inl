@@ -45,7 +45,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
       seg = item / items_per_seg;
       local = item - seg * items_per_seg;
     }
-    const uint32_t y = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
+    const uint32_t y = oop_tile_at(m, (uint32_t)local, balanced);
     tile_outofplace<S, B, VEC, NT>(static_cast<const E*>(src) + seg * seg_elems,
                                    static_cast<E*>(dst) + seg * dst_seg_elems, m, y, lds);
     __syncthreads();
@@ -131,7 +131,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
   uint64_t local;
   const E* in = item_base<E>(const_cast<void*>(src), item, items_per_seg, total_items, seg_elems, &local);
   E* out = static_cast<E*>(dst) + (uint64_t)(in - static_cast<const E*>(src)) / seg_elems * dst_seg_elems;
-  uint32_t y = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
+  uint32_t y = oop_tile_at(m, (uint32_t)local, balanced);
   tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
   while (true) {
     tile_scatter<S, B, VEC, NT, PT>(ra, lds);
@@ -141,7 +141,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
     uint32_t ny = 0;
     if (next < total_items) {
       nin = item_base<E>(const_cast<void*>(src), next, items_per_seg, total_items, seg_elems, &local);
-      ny = balanced ? spread_bits((uint32_t)local, m) : (uint32_t)local;
+      ny = oop_tile_at(m, (uint32_t)local, balanced);
       tile_load<S, B, VEC, NT, PT>(ra, nin, rowstride, ny);
     }
     tile_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
@@ -211,7 +211,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
       if (!pal) tile_store<S, B, VEC, NT, PT>(out, rowstride, y, lds + Sh::TILE_E);
       tile_store<S, B, VEC, NT, PT>(out, rowstride, yr, lds);
     } else {
-      const uint32_t y = spread_bits((uint32_t)local, m);
+      const uint32_t y = oop_tile_at(m, (uint32_t)local, order);
       tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       __syncthreads();
@@ -399,7 +399,7 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched_oop(
     } else {
       const int m = k - 2 * B;
       const uint32_t local = (uint32_t)(item - (uint64_t)scan[a]);
-      const uint32_t y = balanced ? spread_bits(local, m) : local;
+      const uint32_t y = oop_tile_at(m, local, balanced);
       if (((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0) {
         tile_outofplace<S, B, true, NT>(in, out, m, y, lds);
       } else {

@@ -237,6 +237,17 @@ def test_inplace_order_covers_every_pair_once(L, m, order):
     assert L.bitrev_debug_inplace_pair_at(m, count, order) == 0xFFFFFFFF
 
 
+@pytest.mark.parametrize("m", list(range(0, 15)) + [20])
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_outofplace_order_is_a_bijection(L, m, order):
+    """Every out-of-place order visits each source tile of [0, 2^m) once."""
+    ys = np.array([L.bitrev_debug_oop_tile_at(m, w, order) for w in range(2**m)],
+                  dtype=np.int64)
+    assert np.array_equal(np.sort(ys), np.arange(2**m))
+    if m < 32:
+        assert L.bitrev_debug_oop_tile_at(m, 2**m, order) == 0xFFFFFFFF
+
+
 def test_grouped_order_runs_of_neighbouring_tiles(L):
     """The grouped order's first 4^j items (j = 3) touch 2^j runs of 2^j
     neighbouring tiles on each side of the swap."""
