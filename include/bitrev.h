@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define BITREV_ABI_VERSION 1
+#define BITREV_ABI_VERSION 2
 #define BITREV_MAX_LOG2N 40
 
 typedef enum bitrev_status {
@@ -79,6 +79,10 @@ typedef struct bitrev_config {
   int xcd_remap;   /* 0 = choose, 1 = give each XCD a contiguous range of work
                     * items (the dispatcher deals workgroups to the XCDs round
                     * robin), 2 = leave the dispatch order as is */
+  int cache_hints; /* tile kernels' global accesses: 0 = choose, 1 = plain,
+                    * 2 = streaming (non-temporal) loads, 3 = streaming
+                    * stores; applies to one-item-per-workgroup tile kernels
+                    * with 16-byte accesses, otherwise plain */
 } bitrev_config_t;
 
 /* Which code path and geometry a call uses (bitrev_plan_query). */
@@ -99,7 +103,7 @@ typedef struct bitrev_plan {
   int vector_access;    /* 1: 16-byte global accesses; 0: one element per access */
   int variant;          /* 1 one item per workgroup, 2 persistent pipelined */
   int xcd_remap;        /* 1 contiguous ranges per XCD, 2 dispatch order */
-  int reserved;
+  int cache_hints;      /* 1 plain, 2 streaming loads, 3 streaming stores */
   uint64_t work_items;  /* tile pairs (in place) or tiles (out of place), all rows */
   uint64_t lds_bytes;   /* LDS per workgroup */
 } bitrev_plan_t;
@@ -290,8 +294,13 @@ bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_s
 
 /* dst[0 .. bytes) = src[0 .. bytes): a plain streaming copy with the same
  * byte count as an out-of-place permutation, used to measure attainable HBM
- * bandwidth.  Ranges must not overlap. */
+ * bandwidth.  Ranges must not overlap.  bitrev_copy takes the cache hint
+ * measured fastest for the size (streaming loads above 256 MiB, where the
+ * copy no longer fits the Infinity Cache); bitrev_copy_ex takes it from
+ * cache_hints as in bitrev_config_t (0 = that choice). */
 bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream);
+bitrev_status_t bitrev_copy_ex(const void* src, void* dst, size_t bytes, int cache_hints,
+                               void* stream);
 
 const char* bitrev_status_string(bitrev_status_t status);
 int bitrev_last_hip_error(void);

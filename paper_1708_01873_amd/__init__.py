@@ -31,6 +31,7 @@ MODE_INPLACE, MODE_OUTOFPLACE, MODE_BATCHED = 0, 1, 2
 ORDER_DEFAULT, ORDER_NATURAL, ORDER_BALANCED, ORDER_GROUPED = 0, 1, 2, 3
 VARIANT_DEFAULT, VARIANT_ONE_ITEM, VARIANT_PIPELINED = 0, 1, 2
 XCD_DEFAULT, XCD_REMAP, XCD_DISPATCH_ORDER = 0, 1, 2
+HINTS_DEFAULT, HINTS_PLAIN, HINTS_STREAM_LOADS, HINTS_STREAM_STORES = 0, 1, 2, 3
 
 
 class BitrevError(RuntimeError):
@@ -47,7 +48,8 @@ class BitrevError(RuntimeError):
 class Config(ctypes.Structure):
     """bitrev_config_t: zero fields mean "library choice"."""
     _fields_ = [("tile_bits", ctypes.c_int), ("grid_blocks", ctypes.c_int),
-                ("order", ctypes.c_int), ("variant", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
+                ("order", ctypes.c_int), ("variant", ctypes.c_int), ("xcd_remap", ctypes.c_int),
+                ("cache_hints", ctypes.c_int)]
 
 
 class Plan(ctypes.Structure):
@@ -56,11 +58,11 @@ class Plan(ctypes.Structure):
                 ("block_threads", ctypes.c_int), ("grid_blocks", ctypes.c_int),
                 ("order", ctypes.c_int), ("vector_access", ctypes.c_int),
                 ("variant", ctypes.c_int), ("xcd_remap", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("work_items", ctypes.c_uint64),
+                ("cache_hints", ctypes.c_int), ("work_items", ctypes.c_uint64),
                 ("lds_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -82,6 +84,7 @@ _SIGNATURES = {
     "bitrev_load_tuning": ([ctypes.c_char_p], _I),
     "bitrev_tuning_format": ([], ctypes.c_char_p),
     "bitrev_copy": ([_VP, _VP, _SZ, _VP], _I),
+    "bitrev_copy_ex": ([_VP, _VP, _SZ, _I, _VP], _I),
     "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_dit_stages": ([_VP, _VP, _I, _I64, _I, _I, _I, _VP], _I),
     "bitrev_digitrev_inplace": ([_VP, _I, _I, _SZ, _VP], _I),
@@ -142,11 +145,13 @@ def _check(status: int, where: str) -> None:
         raise BitrevError(status, where)
 
 
-def _config(tile_bits=0, grid_blocks=0, order=0, config=None, variant=0, xcd_remap=0):
+def _config(tile_bits=0, grid_blocks=0, order=0, config=None, variant=0, xcd_remap=0,
+            cache_hints=0):
     if config is not None:
         return config
-    if tile_bits or grid_blocks or order or variant or xcd_remap:
-        return Config(int(tile_bits), int(grid_blocks), int(order), int(variant), int(xcd_remap))
+    if tile_bits or grid_blocks or order or variant or xcd_remap or cache_hints:
+        return Config(int(tile_bits), int(grid_blocks), int(order), int(variant), int(xcd_remap),
+                      int(cache_hints))
     return None
 
 
@@ -178,12 +183,12 @@ def _log2_exact(n: int) -> int:
 
 
 def bitrev_inplace(data, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0, order=0,
-                   variant=0, xcd_remap=0, config=None, stream=None):
+                   variant=0, xcd_remap=0, cache_hints=0, config=None, stream=None):
     """Replace ``data`` (2^log2n contiguous elements) by its bit-reversed
     permutation.  ``log2n`` defaults to log2(data.numel())."""
     ptr, s = _tensor_args(data, "data")
     k = _log2_exact(data.numel()) if log2n is None else int(log2n)
-    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
     L = _load()
     if cfg is None:
         _check(L.bitrev_inplace(ptr, k, s, _stream(stream)), "bitrev_inplace")
@@ -194,7 +199,7 @@ def bitrev_inplace(data, log2n: Optional[int] = None, *, tile_bits=0, grid_block
 
 
 def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0,
-                      order=0, variant=0, xcd_remap=0, config=None, stream=None):
+                      order=0, variant=0, xcd_remap=0, cache_hints=0, config=None, stream=None):
     """dst[rev(i)] = src[i]; allocates ``dst`` like ``src`` when not given."""
     if dst is None:
         import torch
@@ -204,7 +209,7 @@ def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0
     if s != s2 or src.numel() != dst.numel():
         raise ValueError("src and dst must have the same element size and length")
     k = _log2_exact(src.numel()) if log2n is None else int(log2n)
-    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
     L = _load()
     if cfg is None:
         _check(L.bitrev_outofplace(sp, dp, k, s, _stream(stream)), "bitrev_outofplace")
@@ -215,7 +220,7 @@ def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0
 
 
 def bitrev_rows(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0,
-                order=0, variant=0, xcd_remap=0, config=None, stream=None):
+                order=0, variant=0, xcd_remap=0, cache_hints=0, config=None, stream=None):
     """Permute every row of 2^log2n elements (default: the last dimension);
     ``dst is src`` works in place.  Allocates ``dst`` when not given."""
     if dst is None:
@@ -235,7 +240,7 @@ def bitrev_rows(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid
     if src.numel() % n:
         raise ValueError("%d elements are not a whole number of rows of %d" % (src.numel(), n))
     rows = src.numel() // n
-    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
     L = _load()
     if cfg is None:
         _check(L.bitrev_rows(sp, dp, k, rows, s, _stream(stream)), "bitrev_rows")
@@ -250,7 +255,7 @@ def bitrev_batched_workspace_size(num_arrays: int) -> int:
 
 
 def bitrev_batched(data, offsets, log2n, workspace=None, *, tile_bits=0, grid_blocks=0, order=0,
-                   variant=0, xcd_remap=0, config=None, stream=None):
+                   variant=0, xcd_remap=0, cache_hints=0, config=None, stream=None):
     """In place on every packed array [offsets[a], offsets[a+1]) of ``data``
     (lengths 2^log2n[a]).  ``offsets`` (int64, num+1) and ``log2n`` (int32,
     num) are device tensors; ``workspace`` is a device byte tensor of at least
@@ -270,7 +275,7 @@ def bitrev_batched(data, offsets, log2n, workspace=None, *, tile_bits=0, grid_bl
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=data.device)
     wp, _ = _tensor_args(workspace, "workspace")
     wbytes = workspace.numel() * workspace.element_size()
-    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
     L = _load()
     if cfg is None:
         _check(L.bitrev_batched(dp, data.numel(), op, lp, num, s, wp, wbytes, _stream(stream)),
@@ -349,14 +354,16 @@ def bitrev_batched_errors(workspace, stream=None) -> tuple[int, int]:
     return nrej.value, first.value
 
 
-def bitrev_copy(src, dst, stream=None):
-    """The reference streaming copy (same bytes as an out-of-place pass)."""
+def bitrev_copy(src, dst, stream=None, *, cache_hints=0):
+    """The reference streaming copy (same bytes as an out-of-place pass);
+    cache_hints as in Config (0: the library's choice for the size)."""
     sp, _ = _tensor_args(src, "src")
     dp, _ = _tensor_args(dst, "dst")
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() < nbytes:
         raise ValueError("dst is smaller than src")
-    _check(_load().bitrev_copy(sp, dp, nbytes, _stream(stream)), "bitrev_copy")
+    _check(_load().bitrev_copy_ex(sp, dp, nbytes, int(cache_hints), _stream(stream)),
+           "bitrev_copy")
     return dst
 
 
@@ -435,9 +442,10 @@ def bitrev_transpose_inplace(data, log2side: Optional[int] = None, *, stream=Non
 
 
 def bitrev_plan_query(log2n: int, elem_size: int, rows: int = 1, mode: int = MODE_INPLACE,
-                      *, tile_bits=0, grid_blocks=0, order=0, variant=0, xcd_remap=0, config=None) -> dict:
+                      *, tile_bits=0, grid_blocks=0, order=0, variant=0, xcd_remap=0,
+                      cache_hints=0, config=None) -> dict:
     """The plan a call would use (no launch)."""
-    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
     p = Plan()
     _check(_load().bitrev_plan_query(int(log2n), int(elem_size), int(rows), int(mode),
                                      ctypes.byref(cfg) if cfg is not None else None,

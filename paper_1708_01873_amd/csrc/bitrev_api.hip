@@ -256,7 +256,7 @@ bool valid_config(const bitrev_config_t* c) {
   if (!c) return true;
   return c->tile_bits >= 0 && c->tile_bits <= kMaxTileBits && c->grid_blocks >= 0 &&
          c->order >= 0 && c->order <= 3 && c->variant >= 0 && c->variant <= 2 &&
-         c->xcd_remap >= 0 && c->xcd_remap <= 2;
+         c->xcd_remap >= 0 && c->xcd_remap <= 2 && c->cache_hints >= 0 && c->cache_hints <= 3;
 }
 
 uint32_t round_up(uint64_t v, uint32_t to) {
@@ -273,6 +273,22 @@ uint32_t default_grid(uint64_t items, const DeviceInfo& d) {
 
 int resident_per_cu(int threads, size_t lds);
 
+// The Infinity Cache of MI355X: arrays beyond it stream through HBM.
+constexpr uint64_t kCacheBytes = 256ull << 20;
+
+// Cache hints of the built-in plans, from a sweep over element sizes and
+// array sizes: out of place, streaming loads never cost and gain most beyond
+// the Infinity Cache (complex64 2^26: +15%, float32 2^28: +10%); in place,
+// streaming loads gain beyond it (+2-5%) while complex64 arrays within it do
+// better with streaming stores (64 MiB: +7%; loads cost 3% at 128 MiB).
+int default_hints(int mode, int s, uint64_t array_bytes, int64_t rows) {
+  const uint64_t total = array_bytes * (uint64_t)(rows > 0 ? rows : 1);
+  if (mode != kModeInplace) return total >= (32ull << 20) ? kHintStreamLoads : kHintPlain;
+  if (total < (64ull << 20)) return kHintPlain;
+  if (s == 8 && total <= kCacheBytes) return kHintStreamStores;
+  return kHintStreamLoads;
+}
+
 struct Plan {
   int path = BITREV_PATH_NONE;
   int b = 0;
@@ -282,6 +298,7 @@ struct Plan {
   int order = 2;
   int variant = 1;
   int xcd_remap = 1;
+  int hints = kHintPlain;  // CacheHint of the one-item 16-byte tile kernels
   bool vec = true;
   uint64_t items_per_seg = 0;
   uint64_t total = 0;
@@ -335,6 +352,8 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
   p->threads = threads_of(s, b, p->vec);
   p->lds = tile_lds_bytes_for(s, b, inplace_tiles);
   p->variant = (cfg && cfg->variant) ? cfg->variant : (te.variant ? te.variant : dp.variant);
+  p->hints = (cfg && cfg->cache_hints) ? cfg->cache_hints - 1
+                                       : default_hints(mode, s, (uint64_t)s << k, rows);
   if (cfg && cfg->grid_blocks > 0) {
     p->grid = round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds);
   } else if (te.wg_per_cu > 0) {
@@ -420,6 +439,7 @@ hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void
   a.xcds = p.xcd_remap == 2 ? 1 : d.xcds;
   a.grid = p.grid;
   a.pipelined = p.variant == 2 ? 1 : 0;
+  a.hints = p.hints;
   switch (s) {
     case 1: return inplace ? launch_tile_inplace_s1(p.b, p.vec, a, st) : launch_tile_outofplace_s1(p.b, p.vec, a, st);
     case 2: return inplace ? launch_tile_inplace_s2(p.b, p.vec, a, st) : launch_tile_outofplace_s2(p.b, p.vec, a, st);
@@ -928,6 +948,7 @@ bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int
   plan->vector_access = p.vec ? 1 : 0;
   plan->variant = p.path == BITREV_PATH_TILE ? p.variant : 0;
   plan->xcd_remap = (p.path == BITREV_PATH_TILE || p.path == BITREV_PATH_BATCHED) ? p.xcd_remap : 0;
+  plan->cache_hints = p.path == BITREV_PATH_TILE ? p.hints + 1 : 0;
   plan->work_items = p.total;
   plan->lds_bytes = p.lds;
   return BITREV_SUCCESS;
@@ -940,16 +961,23 @@ bitrev_status_t bitrev_load_tuning(const char* path) {
 
 const char* bitrev_tuning_format(void) { return kTuningFormat; }
 
-bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream) {
-  if (src == NULL || dst == NULL) return BITREV_ERROR_INVALID_VALUE;
+bitrev_status_t bitrev_copy_ex(const void* src, void* dst, size_t bytes, int cache_hints,
+                               void* stream) {
+  if (src == NULL || dst == NULL || cache_hints < 0 || cache_hints > 3)
+    return BITREV_ERROR_INVALID_VALUE;
   if (bytes == 0) return BITREV_SUCCESS;
   if (overlap(src, dst, bytes)) return BITREV_ERROR_ALIAS;
   DeviceInfo d;
   bitrev_status_t st = device_info(&d, false);
   if (st != BITREV_SUCCESS) return st;
-  const hipError_t e = launch_copy(src, dst, bytes, (uint32_t)(d.cus * 4),
+  const int h = cache_hints ? cache_hints - 1 : (bytes > kCacheBytes ? kHintStreamLoads : kHintPlain);
+  const hipError_t e = launch_copy(src, dst, bytes, (uint32_t)(d.cus * 4), h,
                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  return bitrev_copy_ex(src, dst, bytes, 0, stream);
 }
 
 const char* bitrev_status_string(bitrev_status_t status) {

@@ -87,10 +87,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_batched_prep(const int64_t* of
 // stride.  With four workgroups per compute unit this was the fastest of the
 // copy shapes measured on MI355X (unrolled, blocked and non-temporal forms
 // were slower or equal), so it is the honest denominator for the roofline.
+template <int H>
 __global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src,
                                                 u32x4* __restrict__ dst, uint64_t nvec) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < nvec; i += stride) dst[i] = src[i];
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < nvec; i += stride)
+    st_hint<H>(dst + i, ld_hint<H>(src + i));
 }
 
 __global__ __launch_bounds__(256) void k_copy1(const uint8_t* __restrict__ src,
@@ -107,12 +109,21 @@ hipError_t launch_batched_prep(const BatchedLaunch& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_copy(const void* src, void* dst, size_t bytes, uint32_t grid, hipStream_t st) {
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, uint32_t grid, int hints,
+                       hipStream_t st) {
   const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0;
   const uint64_t nvec = vec ? bytes / 16 : 0;
   if (nvec) {
-    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, static_cast<const u32x4*>(src),
-                       static_cast<u32x4*>(dst), nvec);
+    if (hints == kHintStreamLoads) {
+      hipLaunchKernelGGL(k_copy16<kHintStreamLoads>, dim3(grid), dim3(256), 0, st,
+                         static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), nvec);
+    } else if (hints == kHintStreamStores) {
+      hipLaunchKernelGGL(k_copy16<kHintStreamStores>, dim3(grid), dim3(256), 0, st,
+                         static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), nvec);
+    } else {
+      hipLaunchKernelGGL(k_copy16<kHintPlain>, dim3(grid), dim3(256), 0, st,
+                         static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), nvec);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -36,6 +36,27 @@ template <> struct Bytes<4> { typedef uint32_t T; };
 template <> struct Bytes<8> { typedef u32x2 T; };
 template <> struct Bytes<16> { typedef u32x4 T; };
 
+// Cache hints of the tile kernels' global accesses: streaming
+// (non-temporal) loads or stores mark lines the kernel touches once, so they
+// do not displace other lines in L2 and the Infinity Cache.
+enum CacheHint { kHintPlain = 0, kHintStreamLoads = 1, kHintStreamStores = 2 };
+
+template <int H, typename V> __device__ __forceinline__ V ld_hint(const V* p) {
+  if constexpr (H == kHintStreamLoads) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
+
+template <int H, typename V> __device__ __forceinline__ void st_hint(V* p, V v) {
+  if constexpr (H == kHintStreamStores) {
+    __builtin_nontemporal_store(v, p);
+  } else {
+    *p = v;
+  }
+}
+
 // VB bytes seen either as one vector or as VB/S elements of S bytes.
 template <int S, int VB> union Chunk {
   typename Bytes<VB>::T v;
@@ -281,7 +302,7 @@ __device__ __forceinline__ uint32_t xcd_block(int xcds) {
 // ---------------------------------------------------------------------------
 
 // Load one tile (middle bits y) of the array at `base` into registers.
-template <int S, int B, bool VEC, int NT, int PT>
+template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
 __device__ __forceinline__ void tile_load(Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
                                           const typename Bytes<S>::T* __restrict__ base,
                                           uint64_t rowstride, uint32_t y) {
@@ -294,7 +315,7 @@ __device__ __forceinline__ void tile_load(Chunk<S, TileShape<S, B, VEC>::VB> (&r
       const int x = q / Sh::CPR;
       const int zc = q % Sh::CPR;
       const uint64_t off = (uint64_t)x * rowstride + (uint64_t)y * Sh::R + (uint64_t)(zc * Sh::CE);
-      reg[i].v = *reinterpret_cast<const V*>(base + off);
+      reg[i].v = ld_hint<H>(reinterpret_cast<const V*>(base + off));
     }
   }
 }
@@ -325,7 +346,7 @@ __device__ __forceinline__ void tile_scatter(const Chunk<S, TileShape<S, B, VEC>
 }
 
 // Write the staged tile (destination order in LDS) to tile y of `base`.
-template <int S, int B, bool VEC, int NT, int PT>
+template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
 __device__ __forceinline__ void tile_store(typename Bytes<S>::T* __restrict__ base,
                                            uint64_t rowstride, uint32_t y,
                                            const typename Bytes<S>::T* lds) {
@@ -341,7 +362,7 @@ __device__ __forceinline__ void tile_store(typename Bytes<S>::T* __restrict__ ba
 #pragma unroll
       for (int j = 0; j < Sh::CE; ++j) c.e[j] = lds[r * Sh::PE + cc * Sh::CE + j];
       const uint64_t off = (uint64_t)r * rowstride + (uint64_t)y * Sh::R + (uint64_t)(cc * Sh::CE);
-      *reinterpret_cast<V*>(base + off) = c.v;
+      st_hint<H>(reinterpret_cast<V*>(base + off), c.v);
     }
   }
 }
@@ -349,7 +370,7 @@ __device__ __forceinline__ void tile_store(typename Bytes<S>::T* __restrict__ ba
 // In place: swap tiles y and yr = rev_m(y) of the array at `base` (one tile
 // when y is a palindrome).  Ends with the LDS free for the next item only
 // after the caller's barrier.
-template <int S, int B, bool VEC, int NT>
+template <int S, int B, bool VEC, int NT, int H = kHintPlain>
 __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restrict__ base, int m,
                                                   uint32_t y, typename Bytes<S>::T* lds) {
   typedef TileShape<S, B, VEC> Sh;
@@ -358,19 +379,19 @@ __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restri
   const uint32_t yr = rev_bits(y, m);
   const bool pal = (yr == y);
   Chunk<S, Sh::VB> ra[PT], rb[PT];
-  tile_load<S, B, VEC, NT, PT>(ra, base, rowstride, y);
-  if (!pal) tile_load<S, B, VEC, NT, PT>(rb, base, rowstride, yr);
+  tile_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
+  if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
   tile_scatter<S, B, VEC, NT, PT>(ra, lds);
   if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
   __syncthreads();
   // tile y first, then its partner: measured a few percent faster than the
   // other order for arrays that fit the Infinity Cache
-  if (!pal) tile_store<S, B, VEC, NT, PT>(base, rowstride, y, lds + Sh::TILE_E);
-  tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
+  if (!pal) tile_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds + Sh::TILE_E);
+  tile_store<S, B, VEC, NT, PT, H>(base, rowstride, yr, lds);
 }
 
 // Out of place: tile y of `src` to tile rev_m(y) of `dst`.
-template <int S, int B, bool VEC, int NT>
+template <int S, int B, bool VEC, int NT, int H = kHintPlain>
 __device__ __forceinline__ void tile_outofplace(const typename Bytes<S>::T* __restrict__ src,
                                                 typename Bytes<S>::T* __restrict__ dst, int m,
                                                 uint32_t y, typename Bytes<S>::T* lds) {
@@ -378,10 +399,10 @@ __device__ __forceinline__ void tile_outofplace(const typename Bytes<S>::T* __re
   constexpr int PT = (Sh::CPT + NT - 1) / NT;
   const uint64_t rowstride = 1ull << (m + B);
   Chunk<S, Sh::VB> ra[PT];
-  tile_load<S, B, VEC, NT, PT>(ra, src, rowstride, y);
+  tile_load<S, B, VEC, NT, PT, H>(ra, src, rowstride, y);
   tile_scatter<S, B, VEC, NT, PT>(ra, lds);
   __syncthreads();
-  tile_store<S, B, VEC, NT, PT>(dst, rowstride, rev_bits(y, m), lds);
+  tile_store<S, B, VEC, NT, PT, H>(dst, rowstride, rev_bits(y, m), lds);
 }
 
 // ---------------------------------------------------------------------------

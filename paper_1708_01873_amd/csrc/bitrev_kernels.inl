@@ -12,7 +12,7 @@ namespace {
 
 // In place, one array or `total_items / items_per_seg` equal arrays: work
 // item -> (array, pair y <= rev_m(y)) -> swap the two tiles through LDS.
-template <int S, int B, bool VEC>
+template <int S, int B, bool VEC, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace(
     void* data, int m, uint64_t items_per_seg, uint64_t total_items, uint64_t seg_elems,
     int balanced, int xcds) {
@@ -26,13 +26,13 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace(
       local = item - seg * items_per_seg;
     }
     const uint32_t y = inplace_pair_at(m, local, balanced);
-    tile_pair_inplace<S, B, VEC, NT>(static_cast<E*>(data) + seg * seg_elems, m, y, lds);
+    tile_pair_inplace<S, B, VEC, NT, H>(static_cast<E*>(data) + seg * seg_elems, m, y, lds);
     __syncthreads();
   }
 }
 
 // Out of place: work item -> (array, tile y) -> tile rev_m(y) of dst.
-template <int S, int B, bool VEC>
+template <int S, int B, bool VEC, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
     uint64_t seg_elems, uint64_t dst_seg_elems, int balanced, int xcds) {
@@ -46,8 +46,8 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
       local = item - seg * items_per_seg;
     }
     const uint32_t y = oop_tile_at(m, (uint32_t)local, balanced);
-    tile_outofplace<S, B, VEC, NT>(static_cast<const E*>(src) + seg * seg_elems,
-                                   static_cast<E*>(dst) + seg * dst_seg_elems, m, y, lds);
+    tile_outofplace<S, B, VEC, NT, H>(static_cast<const E*>(src) + seg * seg_elems,
+                                      static_cast<E*>(dst) + seg * dst_seg_elems, m, y, lds);
     __syncthreads();
   }
 }
@@ -417,9 +417,21 @@ hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
                        a.total_items, a.seg_elems, a.balanced, a.xcds);
   } else {
-    hipLaunchKernelGGL((k_tile_inplace<S, B, VEC>), dim3(a.grid), dim3(tile_threads<S, B, VEC>()),
-                       0, st, a.dst, a.m, a.items_per_seg, a.total_items, a.seg_elems, a.balanced,
-                       a.xcds);
+    // cache hints only on the 16-byte form; the per-element form stays plain
+    const int h = VEC ? a.hints : kHintPlain;
+    if (h == kHintStreamLoads) {
+      hipLaunchKernelGGL((k_tile_inplace<S, B, VEC, kHintStreamLoads>), dim3(a.grid),
+                         dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
+                         a.total_items, a.seg_elems, a.balanced, a.xcds);
+    } else if (h == kHintStreamStores) {
+      hipLaunchKernelGGL((k_tile_inplace<S, B, VEC, kHintStreamStores>), dim3(a.grid),
+                         dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
+                         a.total_items, a.seg_elems, a.balanced, a.xcds);
+    } else {
+      hipLaunchKernelGGL((k_tile_inplace<S, B, VEC, kHintPlain>), dim3(a.grid),
+                         dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
+                         a.total_items, a.seg_elems, a.balanced, a.xcds);
+    }
   }
   return hipGetLastError();
 }
@@ -431,9 +443,23 @@ hipError_t run_tile_outofplace(const TileLaunch& a, hipStream_t st) {
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
                        a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced, a.xcds);
   } else {
-    hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC>), dim3(a.grid),
-                       dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
-                       a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced, a.xcds);
+    const int h = VEC ? a.hints : kHintPlain;
+    if (h == kHintStreamLoads) {
+      hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC, kHintStreamLoads>), dim3(a.grid),
+                         dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m,
+                         a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced,
+                         a.xcds);
+    } else if (h == kHintStreamStores) {
+      hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC, kHintStreamStores>), dim3(a.grid),
+                         dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m,
+                         a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced,
+                         a.xcds);
+    } else {
+      hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC, kHintPlain>), dim3(a.grid),
+                         dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m,
+                         a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced,
+                         a.xcds);
+    }
   }
   return hipGetLastError();
 }
@@ -446,10 +472,10 @@ int occupancy_of(bool inplace, bool pipelined) {
   const int nt = tile_threads<S, B, VEC>();
   if (inplace) {
     e = pipelined ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_inplace_pipe<S, B, VEC>, nt, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_inplace<S, B, VEC>, nt, 0);
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_inplace<S, B, VEC, kHintPlain>, nt, 0);
   } else {
     e = pipelined ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_outofplace_pipe<S, B, VEC>, nt, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_outofplace<S, B, VEC>, nt, 0);
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_outofplace<S, B, VEC, kHintPlain>, nt, 0);
   }
   return e == hipSuccess ? n : 0;
 }

@@ -28,6 +28,7 @@ struct TileLaunch {
   int xcds;                 // number of XCDs the grid is dealt over
   uint32_t grid;            // workgroups (multiple of xcds)
   int pipelined;            // 1: persistent software-pipelined kernel
+  int hints = 0;            // CacheHint of the one-item 16-byte kernels
 };
 
 struct WaveLaunch {
@@ -104,6 +105,7 @@ hipError_t launch_dit_s8(int b, bool vec, const DitLaunch& a, hipStream_t st);
 hipError_t launch_dit_s16(int b, bool vec, const DitLaunch& a, hipStream_t st);
 
 hipError_t launch_batched_prep(const BatchedLaunch& a, hipStream_t st);
-hipError_t launch_copy(const void* src, void* dst, size_t bytes, uint32_t grid, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, uint32_t grid, int hints,
+                       hipStream_t st);
 
 }  // namespace bitrev

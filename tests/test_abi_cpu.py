@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert br.abi_version() == 1
+    assert br.abi_version() == 2
     for st in range(6):
         assert br.status_string(st)
     assert br.status_string(99) == "unknown status"
@@ -90,7 +90,7 @@ def test_rows_validation(L):
 def test_config_validation(L):
     for cfg in (br.Config(8, 0, 0, 0), br.Config(-1, 0, 0, 0), br.Config(0, -5, 0, 0),
                 br.Config(0, 0, 4, 0), br.Config(0, 0, 0, 3), br.Config(0, 0, 0, -1),
-                br.Config(0, 0, 0, 0, 3)):
+                br.Config(0, 0, 0, 0, 3), br.Config(0, 0, 0, 0, 0, 4), br.Config(0, 0, 0, 0, 0, -1)):
         assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
 
 
@@ -120,6 +120,8 @@ def test_batched_validation(L):
 
 
 def test_copy_validation(L):
+    assert L.bitrev_copy_ex(FAKE, FAKE + 64, 16, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_ex(FAKE, FAKE + 64, 16, -1, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_copy(FAKE, FAKE + 8, 16, None) == br.ERROR_ALIAS
     assert L.bitrev_copy(None, FAKE, 16, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_copy(FAKE, FAKE + 64, 0, None) == br.SUCCESS
@@ -134,8 +136,13 @@ def test_plan_query_defaults(L):
     # grouped order, one item per workgroup, dispatch order
     p = br.bitrev_plan_query(24, 8)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
+    assert p["cache_hints"] == br.HINTS_STREAM_STORES
     p = br.bitrev_plan_query(28, 8)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
+    assert p["cache_hints"] == br.HINTS_STREAM_LOADS  # beyond the Infinity Cache
+    assert br.bitrev_plan_query(24, 8, cache_hints=br.HINTS_PLAIN)["cache_hints"] == 1
+    assert br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)["cache_hints"] == 2
+    assert br.bitrev_plan_query(20, 8)["cache_hints"] == 1  # small arrays: plain
     p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 1, 2, 1)
     assert p["work_items"] == 2**14

@@ -96,6 +96,37 @@ def test_element_aligned_base(s):
             assert_bytes_equal(got, want, "misaligned s=%d k=%d ip=%s" % (s, k, inplace))
 
 
+@pytest.mark.parametrize("s", ELEM_SIZES)
+def test_cache_hints(s):
+    """Every cache-hint instance of the one-item tile kernels (plain,
+    streaming loads, streaming stores), every order, in and out of place,
+    16-byte and per-element access, against the oracle."""
+    for k in (13, 16):
+        host = workloads.byte_pattern((1 << k) * s, seed=31 * s + k)
+        want = oracle.outofplace(host, s)
+        for hints in (br.HINTS_PLAIN, br.HINTS_STREAM_LOADS, br.HINTS_STREAM_STORES):
+            for inplace in (True, False):
+                for order in (1, 2, 3):
+                    for pad in (0, 1):
+                        if pad and s >= 16:
+                            continue
+                        got = _run(host, k, s, inplace, pad_front=pad, variant=1, order=order,
+                                   cache_hints=hints)
+                        assert_bytes_equal(got, want, "s=%d k=%d hints=%d ip=%s order=%d pad=%d"
+                                           % (s, k, hints, inplace, order, pad))
+
+
+def test_copy_hints():
+    """The reference copy with each cache hint copies every byte."""
+    for nbytes in (1 << 20, (1 << 20) + 7):
+        host = workloads.byte_pattern(nbytes, seed=nbytes)
+        x = torch.from_numpy(host).cuda()
+        for hints in (0, 1, 2, 3):
+            y = torch.zeros_like(x)
+            br.bitrev_copy(x, y, cache_hints=hints)
+            assert_bytes_equal(y.cpu().numpy(), host, "copy hints=%d n=%d" % (hints, nbytes))
+
+
 @pytest.mark.parametrize("grid", [8, 24, 64])
 def test_persistent_grid(grid):
     """A small explicit grid makes every workgroup loop over many items."""
