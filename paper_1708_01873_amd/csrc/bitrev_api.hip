@@ -87,6 +87,7 @@ struct TuneEntry {
   int order = 0;
   int variant = 0;
   int xcd_remap = 0;
+  int cache_hints = 0;
 };
 
 std::mutex g_tune_mu;
@@ -94,11 +95,12 @@ std::map<std::tuple<int, int, int>, TuneEntry> g_tune;
 std::once_flag g_tune_env_once;
 
 const char kTuningFormat[] =
-    "libbitrev tuning v1: one entry per line, '#' starts a comment; fields: mode "
+    "libbitrev tuning v2: one entry per line, '#' starts a comment; fields: mode "
     "(inplace|outofplace|batched) elem_size log2n(-1 = any) tile_bits(0 = default) "
-    "wg_per_cu(0 = default) order(0 = default, 1 natural, 2 balanced) "
+    "wg_per_cu(0 = default) order(0 = default, 1 natural, 2 balanced, 3 grouped) "
     "variant(0 = default, 1 one item per workgroup, 2 persistent pipelined) "
-    "xcd_remap(0 = default, 1 contiguous ranges per XCD, 2 dispatch order)";
+    "xcd_remap(0 = default, 1 contiguous ranges per XCD, 2 dispatch order) "
+    "[cache_hints(0 = default, 1 plain, 2 streaming loads, 3 streaming stores)]";
 
 int mode_from_name(const char* s) {
   if (strcmp(s, "inplace") == 0) return 0;
@@ -124,15 +126,15 @@ bitrev_status_t load_tuning_file(const char* path) {
     char* hash = strchr(line, '#');
     if (hash) *hash = '\0';
     char mode[32];
-    int s, k, b, wg, order, variant, xcd;
+    int s, k, b, wg, order, variant, xcd, hints = 0;
     char extra[8];
-    const int got = sscanf(line, "%31s %d %d %d %d %d %d %d %7s", mode, &s, &k, &b, &wg, &order,
-                           &variant, &xcd, extra);
+    const int got = sscanf(line, "%31s %d %d %d %d %d %d %d %d %7s", mode, &s, &k, &b, &wg,
+                           &order, &variant, &xcd, &hints, extra);
     if (got <= 0) continue;  // blank or comment-only line
     const int md = got >= 8 ? mode_from_name(mode) : -1;
-    if (got != 8 || md < 0 || !valid_elem_size((size_t)s) || k < -1 || k > BITREV_MAX_LOG2N ||
-        b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 || order > 2 ||
-        variant < 0 || variant > 2 || xcd < 0 || xcd > 2) {
+    if ((got != 8 && got != 9) || md < 0 || !valid_elem_size((size_t)s) || k < -1 ||
+        k > BITREV_MAX_LOG2N || b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 ||
+        order > 3 || variant < 0 || variant > 2 || xcd < 0 || xcd > 2 || hints < 0 || hints > 3) {
       ok = false;
       break;
     }
@@ -142,6 +144,7 @@ bitrev_status_t load_tuning_file(const char* path) {
     t.order = order;
     t.variant = variant;
     t.xcd_remap = xcd;
+    t.cache_hints = hints;
     table[std::make_tuple(md, s, k)] = t;
   }
   fclose(f);
@@ -352,8 +355,9 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
   p->threads = threads_of(s, b, p->vec);
   p->lds = tile_lds_bytes_for(s, b, inplace_tiles);
   p->variant = (cfg && cfg->variant) ? cfg->variant : (te.variant ? te.variant : dp.variant);
-  p->hints = (cfg && cfg->cache_hints) ? cfg->cache_hints - 1
-                                       : default_hints(mode, s, (uint64_t)s << k, rows);
+  p->hints = (cfg && cfg->cache_hints)
+                 ? cfg->cache_hints - 1
+                 : (te.cache_hints ? te.cache_hints - 1 : default_hints(mode, s, (uint64_t)s << k, rows));
   if (cfg && cfg->grid_blocks > 0) {
     p->grid = round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds);
   } else if (te.wg_per_cu > 0) {
@@ -734,6 +738,7 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
   a.t.xcds = dp.xcd_remap == 2 ? 1 : d.xcds;  // the plain kernel's choice for this size
   a.t.grid = default_grid(a.t.total_items, d);
   a.t.pipelined = 0;
+  a.t.hints = default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, rows);
   a.stages = stages;
   a.inverse = inverse;
   const size_t vb = (s << b) < 16 ? (s << b) : 16;

@@ -175,7 +175,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_transpose_inpla
 // elements), out of place (src != dst) or in place (src == dst, tile pairs).
 // Bit reversal fused with the first `stages` radix-2 DIT levels (complex
 // elements), in place (tile pairs) or out of place.
-template <int S, int B, bool VEC, bool INPLACE>
+template <int S, int B, bool VEC, bool INPLACE, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
     uint64_t seg_elems, int stages, int inverse, int order, int xcds) {
@@ -202,40 +202,49 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
       const uint32_t y = inplace_pair_at(m, local, order);
       const uint32_t yr = rev_bits(y, m);
       const bool pal = (y == yr);
-      tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
-      if (!pal) tile_load<S, B, VEC, NT, PT>(rb, in, rowstride, yr);
+      tile_load<S, B, VEC, NT, PT, H>(ra, in, rowstride, y);
+      if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, in, rowstride, yr);
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
       __syncthreads();
       dit_rows<S, B, NT>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw);
-      if (!pal) tile_store<S, B, VEC, NT, PT>(out, rowstride, y, lds + Sh::TILE_E);
-      tile_store<S, B, VEC, NT, PT>(out, rowstride, yr, lds);
+      if (!pal) tile_store<S, B, VEC, NT, PT, H>(out, rowstride, y, lds + Sh::TILE_E);
+      tile_store<S, B, VEC, NT, PT, H>(out, rowstride, yr, lds);
     } else {
       const uint32_t y = oop_tile_at(m, (uint32_t)local, order);
-      tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
+      tile_load<S, B, VEC, NT, PT, H>(ra, in, rowstride, y);
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       __syncthreads();
       dit_rows<S, B, NT>(lds, Sh::R, stages, inverse != 0, tw);
-      tile_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
+      tile_store<S, B, VEC, NT, PT, H>(out, rowstride, rev_bits(y, m), lds);
     }
     __syncthreads();
   }
 }
 
-template <int S, int B, bool VEC>
-hipError_t run_dit(const DitLaunch& a, hipStream_t st) {
+template <int S, int B, bool VEC, int H>
+hipError_t run_dit_h(const DitLaunch& a, hipStream_t st) {
   if (a.t.src == a.t.dst) {
-    hipLaunchKernelGGL((k_tile_dit<S, B, VEC, true>), dim3(a.t.grid),
+    hipLaunchKernelGGL((k_tile_dit<S, B, VEC, true, H>), dim3(a.t.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.t.src, a.t.dst, a.t.m,
                        a.t.items_per_seg, a.t.total_items, a.t.seg_elems, a.stages, a.inverse,
                        a.t.balanced, a.t.xcds);
   } else {
-    hipLaunchKernelGGL((k_tile_dit<S, B, VEC, false>), dim3(a.t.grid),
+    hipLaunchKernelGGL((k_tile_dit<S, B, VEC, false, H>), dim3(a.t.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.t.src, a.t.dst, a.t.m,
                        a.t.items_per_seg, a.t.total_items, a.t.seg_elems, a.stages, a.inverse,
                        a.t.balanced, a.t.xcds);
   }
   return hipGetLastError();
+}
+
+// Cache hints as for the one-item tile kernels (16-byte form only).
+template <int S, int B, bool VEC>
+hipError_t run_dit(const DitLaunch& a, hipStream_t st) {
+  const int h = VEC ? a.t.hints : kHintPlain;
+  if (h == kHintStreamLoads) return run_dit_h<S, B, VEC, kHintStreamLoads>(a, st);
+  if (h == kHintStreamStores) return run_dit_h<S, B, VEC, kHintStreamStores>(a, st);
+  return run_dit_h<S, B, VEC, kHintPlain>(a, st);
 }
 
 template <int S, int B = 1>

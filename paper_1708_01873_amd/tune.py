@@ -44,16 +44,17 @@ class Candidate:
     variant: int = 0
     wg_per_cu: int = 0
     xcd_remap: int = 0
+    cache_hints: int = 0
     ms: float = float("inf")
 
     def line(self, mode: int, elem_size: int, log2n: int) -> str:
-        return "%s %d %d %d %d %d %d %d" % (MODE_NAMES[mode], elem_size, log2n, self.tile_bits,
-                                            self.wg_per_cu, self.order, self.variant,
-                                            self.xcd_remap)
+        return "%s %d %d %d %d %d %d %d %d" % (MODE_NAMES[mode], elem_size, log2n, self.tile_bits,
+                                               self.wg_per_cu, self.order, self.variant,
+                                               self.xcd_remap, self.cache_hints)
 
     def config(self) -> dict:
         return dict(tile_bits=self.tile_bits, order=self.order, variant=self.variant,
-                    xcd_remap=self.xcd_remap)
+                    xcd_remap=self.xcd_remap, cache_hints=self.cache_hints)
 
 
 @dataclass
@@ -107,10 +108,12 @@ def plain_candidates(log2n: int, elem_size: int, mode: int) -> list[Candidate]:
     for b in range(1, MAX_TILE_BITS[elem_size] + 1):
         if 2 * b > log2n or (elem_size << b) < 16:
             continue
-        for order in (1, 2):
+        for order in (1, 2, 3):
             for variant in (1, 2):
                 for xcd in (1, 2):
-                    out.append(Candidate(b, order, variant, 0, xcd))
+                    # cache hints apply to the one-item kernels only
+                    for hints in ((1, 2, 3) if variant == 1 else (0,)):
+                        out.append(Candidate(b, order, variant, 0, xcd, hints))
     return out
 
 
@@ -156,7 +159,7 @@ def tune_plain(log2n: int, elem_size: int, mode: int = MODE_INPLACE, *, rows: in
 
 
 def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 1, 2, 4, 8),
-                 tile_bits=None, orders=(1, 2), xcd_remaps=(1, 2)) -> TuneResult:
+                 tile_bits=None, orders=(1, 2, 3), xcd_remaps=(1, 2)) -> TuneResult:
     """Time the batched launch on the caller's own batch (device tensors as
     for bitrev_batched) over tile widths, orders and workgroups per CU.  Each
     candidate runs an even number of times, so `data` ends unchanged."""
@@ -193,7 +196,7 @@ def write_tuning(results: list[TuneResult], path: str, note: str = "") -> str:
     """Write the best plan of each result as a libbitrev tuning table."""
     props = torch.cuda.get_device_properties(0)
     lines = ["# libbitrev tuning table (mode elem_size log2n tile_bits wg_per_cu order variant "
-             "xcd_remap)",
+             "xcd_remap cache_hints)",
              "# device: %s, %d compute units%s" % (props.name, props.multi_processor_count,
                                                    ("; " + note) if note else "")]
     for r in results:
@@ -248,10 +251,11 @@ def main() -> None:
         batch = (data, torch.from_numpy(offsets).cuda(), torch.from_numpy(l2).cuda())
     path = args.out or default_cache_path()
     for r in autotune(path, plain, batch, reps=args.reps):
-        print("%-10s s=%-2d k=%-3d best b=%d order=%d variant=%d xcd=%d wg/cu=%d  %.4f ms  "
-              "(%.3fx built-in)" % (MODE_NAMES[r.mode], r.elem_size, r.log2n, r.best.tile_bits,
-                                    r.best.order, r.best.variant, r.best.xcd_remap,
-                                    r.best.wg_per_cu, r.best.ms, r.gain_over_default))
+        print("%-10s s=%-2d k=%-3d best b=%d order=%d variant=%d xcd=%d hints=%d wg/cu=%d  "
+              "%.4f ms  (%.3fx built-in)" % (MODE_NAMES[r.mode], r.elem_size, r.log2n,
+                                             r.best.tile_bits, r.best.order, r.best.variant,
+                                             r.best.xcd_remap, r.best.cache_hints,
+                                             r.best.wg_per_cu, r.best.ms, r.gain_over_default))
     print("wrote", path)
 
 

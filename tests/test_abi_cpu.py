@@ -185,12 +185,14 @@ def test_tuning_file(L, tmp_path):
         p = br.bitrev_plan_query(24, 8)
         assert (p["tile_bits"], p["order"], p["variant"], p["xcd_remap"]) == (5, 2, 1, 2)
         assert br.bitrev_plan_query(25, 8)["tile_bits"] == 6  # no entry: default
+        assert br.bitrev_plan_query(24, 8)["cache_hints"] == 3  # 8 fields: default hint
         p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
         assert p["tile_bits"] == 4 and p["order"] == 1 and p["grid_blocks"] == 4 * 256
         for bad in ("inplace 8 24 6 0 2 0\n", "sideways 8 24 6 0 2 0 0\n",
                     "inplace 3 24 6 0 2 0 0\n", "inplace 8 24 9 0 2 0 0\n",
                     "inplace 8 24 6 0 2 3 0\n", "inplace 8 24 6 0 2 0 3\n",
-                    "inplace 8 24 6 0 2 0 0 7\n"):
+                    "inplace 8 24 6 0 2 0 0 7\n", "inplace 8 24 6 0 2 0 0 1 1\n",
+                    "inplace 8 24 6 0 4 0 0\n"):
             f = tmp_path / "bad.txt"
             f.write_text(bad)
             with pytest.raises(br.BitrevError):
@@ -199,6 +201,12 @@ def test_tuning_file(L, tmp_path):
             assert br.bitrev_plan_query(24, 8)["tile_bits"] == 5
         with pytest.raises(br.BitrevError):
             br.bitrev_load_tuning(str(tmp_path / "missing.txt"))
+        v2 = tmp_path / "tune_v2.txt"
+        v2.write_text("outofplace 4 26 7 0 3 1 1 2\n")
+        br.bitrev_load_tuning(str(v2))
+        p = br.bitrev_plan_query(26, 4, mode=br.MODE_OUTOFPLACE)
+        assert (p["tile_bits"], p["order"], p["variant"], p["xcd_remap"], p["cache_hints"]) == \
+            (7, 3, 1, 1, 2)
     finally:
         br.bitrev_load_tuning(None)
     assert br.bitrev_plan_query(24, 8)["tile_bits"] == 6

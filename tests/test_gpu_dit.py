@@ -65,10 +65,18 @@ def test_dit_rows_and_full_size():
     got = to_host_bytes(y).view(np.complex64).reshape(9, -1)
     for r in range(9):
         _check(got[r], x[r], 6, False, np.complex64)
+    # 128 MiB: in place the plan streams the stores, out of place the loads
     x = workloads.complex64_normal(24, workloads.SEEDS["c2"])
     t = torch.from_numpy(x).cuda()
+    y = br.bitrev_dit_stages(t, stages=6)
+    _check(to_host_bytes(y).view(np.complex64), x, 6, False, np.complex64)
     br.bitrev_dit_stages(t, t, stages=6)
     _check(to_host_bytes(t).view(np.complex64), x, 6, False, np.complex64)
+    # complex128, 128 MiB in place: streaming loads on the 16-byte kernel
+    x = _data(23, 1, np.complex128, 5)
+    t = torch.from_numpy(x).cuda()
+    br.bitrev_dit_stages(t, t, stages=3, inverse=True)
+    _check(to_host_bytes(t).view(np.complex128), x, 3, True, np.complex128)
 
 
 def test_dit_rejects():

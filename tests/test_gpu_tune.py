@@ -30,6 +30,8 @@ def test_tune_plain_and_load(tmp_path):
         p = br.bitrev_plan_query(18, 8)
         assert (p["tile_bits"], p["order"], p["variant"]) == (
             r_ip.best.tile_bits, r_ip.best.order, r_ip.best.variant)
+        if r_ip.best.cache_hints:
+            assert p["cache_hints"] == r_ip.best.cache_hints
         # the tuned plan still computes the permutation
         host = workloads.complex64_normal(18, 3)
         x = torch.from_numpy(host).cuda()
