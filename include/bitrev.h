@@ -75,7 +75,11 @@ typedef struct bitrev_config {
                     * workgroup, 2 = persistent and software-pipelined (each
                     * workgroup loads its next tiles while storing the
                     * current ones; grid = resident workgroups unless
-                    * grid_blocks is set) */
+                    * grid_blocks is set), 3 = register-staged (in place:
+                    * half the threads hold the pair in registers and
+                    * transpose its tiles in turn through one LDS tile, so
+                    * twice the pairs are in flight per compute unit; out of
+                    * place it is variant 1) */
   int xcd_remap;   /* 0 = choose, 1 = give each XCD a contiguous range of work
                     * items (the dispatcher deals workgroups to the XCDs round
                     * robin), 2 = leave the dispatch order as is */
@@ -101,7 +105,7 @@ typedef struct bitrev_plan {
   int grid_blocks;      /* workgroups launched */
   int order;            /* 1 natural, 2 balanced, 3 grouped */
   int vector_access;    /* 1: 16-byte global accesses; 0: one element per access */
-  int variant;          /* 1 one item per workgroup, 2 persistent pipelined */
+  int variant;          /* 1 one item per workgroup, 2 persistent pipelined, 3 register-staged */
   int xcd_remap;        /* 1 contiguous ranges per XCD, 2 dispatch order */
   int cache_hints;      /* 1 plain, 2 streaming loads, 3 streaming stores */
   uint64_t work_items;  /* tile pairs (in place) or tiles (out of place), all rows */

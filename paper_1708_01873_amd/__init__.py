@@ -29,7 +29,7 @@ ERROR_NOT_SUPPORTED = 5
 PATH_NONE, PATH_WAVE, PATH_TILE, PATH_BATCHED = 0, 1, 2, 3
 MODE_INPLACE, MODE_OUTOFPLACE, MODE_BATCHED = 0, 1, 2
 ORDER_DEFAULT, ORDER_NATURAL, ORDER_BALANCED, ORDER_GROUPED = 0, 1, 2, 3
-VARIANT_DEFAULT, VARIANT_ONE_ITEM, VARIANT_PIPELINED = 0, 1, 2
+VARIANT_DEFAULT, VARIANT_ONE_ITEM, VARIANT_PIPELINED, VARIANT_REGISTER_STAGED = 0, 1, 2, 3
 XCD_DEFAULT, XCD_REMAP, XCD_DISPATCH_ORDER = 0, 1, 2
 HINTS_DEFAULT, HINTS_PLAIN, HINTS_STREAM_LOADS, HINTS_STREAM_STORES = 0, 1, 2, 3
 

@@ -98,7 +98,7 @@ const char kTuningFormat[] =
     "libbitrev tuning v2: one entry per line, '#' starts a comment; fields: mode "
     "(inplace|outofplace|batched) elem_size log2n(-1 = any) tile_bits(0 = default) "
     "wg_per_cu(0 = default) order(0 = default, 1 natural, 2 balanced, 3 grouped) "
-    "variant(0 = default, 1 one item per workgroup, 2 persistent pipelined) "
+    "variant(0 = default, 1 one item per workgroup, 2 persistent pipelined, 3 register-staged) "
     "xcd_remap(0 = default, 1 contiguous ranges per XCD, 2 dispatch order) "
     "[cache_hints(0 = default, 1 plain, 2 streaming loads, 3 streaming stores)]";
 
@@ -134,7 +134,7 @@ bitrev_status_t load_tuning_file(const char* path) {
     const int md = got >= 8 ? mode_from_name(mode) : -1;
     if ((got != 8 && got != 9) || md < 0 || !valid_elem_size((size_t)s) || k < -1 ||
         k > BITREV_MAX_LOG2N || b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 ||
-        order > 3 || variant < 0 || variant > 2 || xcd < 0 || xcd > 2 || hints < 0 || hints > 3) {
+        order > 3 || variant < 0 || variant > 3 || xcd < 0 || xcd > 2 || hints < 0 || hints > 3) {
       ok = false;
       break;
     }
@@ -234,6 +234,16 @@ int occupancy_of(int s, int b, bool vec, bool inplace, bool pipelined) {
   }
 }
 
+int rs_threads_of(int s, int b, bool vec) {
+  switch (s) {
+    case 1: return tile_rs_threads_s1(b, vec);
+    case 2: return tile_rs_threads_s2(b, vec);
+    case 4: return tile_rs_threads_s4(b, vec);
+    case 8: return tile_rs_threads_s8(b, vec);
+    default: return tile_rs_threads_s16(b, vec);
+  }
+}
+
 int threads_of(int s, int b, bool vec) {
   switch (s) {
     case 1: return tile_threads_s1(b, vec);
@@ -258,7 +268,7 @@ int order_code(int order) {
 bool valid_config(const bitrev_config_t* c) {
   if (!c) return true;
   return c->tile_bits >= 0 && c->tile_bits <= kMaxTileBits && c->grid_blocks >= 0 &&
-         c->order >= 0 && c->order <= 3 && c->variant >= 0 && c->variant <= 2 &&
+         c->order >= 0 && c->order <= 3 && c->variant >= 0 && c->variant <= 3 &&
          c->xcd_remap >= 0 && c->xcd_remap <= 2 && c->cache_hints >= 0 && c->cache_hints <= 3;
 }
 
@@ -329,7 +339,10 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
     p->total = (uint64_t)rows;
     return BITREV_SUCCESS;
   }
-  const int inplace_tiles = (mode == kModeInplace) ? 2 : 1;
+  p->variant = (cfg && cfg->variant) ? cfg->variant : (te.variant ? te.variant : dp.variant);
+  if (p->variant == 3 && mode != kModeInplace) p->variant = 1;  // register staging is in place only
+  // LDS tiles per workgroup: a pair in place (one when register-staged)
+  const int inplace_tiles = (mode == kModeInplace && p->variant != 3) ? 2 : 1;
   int b;
   if (forced_b > 0) {
     b = forced_b;
@@ -352,9 +365,8 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
   p->items_per_seg = (mode == kModeInplace) ? pair_count(m) : (1ull << m);
   if ((uint64_t)rows > (1ull << 62) / p->items_per_seg) return BITREV_ERROR_NOT_SUPPORTED;
   p->total = p->items_per_seg * (uint64_t)rows;
-  p->threads = threads_of(s, b, p->vec);
+  p->threads = p->variant == 3 ? rs_threads_of(s, b, p->vec) : threads_of(s, b, p->vec);
   p->lds = tile_lds_bytes_for(s, b, inplace_tiles);
-  p->variant = (cfg && cfg->variant) ? cfg->variant : (te.variant ? te.variant : dp.variant);
   p->hints = (cfg && cfg->cache_hints)
                  ? cfg->cache_hints - 1
                  : (te.cache_hints ? te.cache_hints - 1 : default_hints(mode, s, (uint64_t)s << k, rows));
@@ -442,7 +454,7 @@ hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void
   a.balanced = order_code(p.order);
   a.xcds = p.xcd_remap == 2 ? 1 : d.xcds;
   a.grid = p.grid;
-  a.pipelined = p.variant == 2 ? 1 : 0;
+  a.pipelined = p.variant == 2 ? 1 : (p.variant == 3 ? 2 : 0);
   a.hints = p.hints;
   switch (s) {
     case 1: return inplace ? launch_tile_inplace_s1(p.b, p.vec, a, st) : launch_tile_outofplace_s1(p.b, p.vec, a, st);

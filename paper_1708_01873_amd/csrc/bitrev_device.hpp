@@ -287,6 +287,15 @@ template <int S, int B, bool VEC> constexpr int tile_threads() {
   return c < 64 ? 64 : (c > 1024 ? 1024 : c);
 }
 
+// Threads per workgroup of the register-staged in-place kernel: four
+// accesses per thread per tile (half the plain kernel's threads), so that
+// twice as many workgroups, each holding its tile pair in registers, fit on
+// a compute unit.
+template <int S, int B, bool VEC> constexpr int rs_threads() {
+  constexpr int c = TileShape<S, B, VEC>::CPT / 4;
+  return c < 64 ? 64 : (c > 512 ? 512 : c);
+}
+
 // Logical block index: the hardware deals workgroups to the XCDs round
 // robin, so block i runs on XCD i % xcds.  Renumber so that each XCD owns a
 // contiguous range of work items; neighbouring work items then share its L2
@@ -365,6 +374,74 @@ __device__ __forceinline__ void tile_store(typename Bytes<S>::T* __restrict__ ba
       st_hint<H>(reinterpret_cast<V*>(base + off), c.v);
     }
   }
+}
+
+// LDS -> registers in the order tile_store writes: chunk i of this thread
+// is LDS row r, chunk cc (destination row r of the tile).
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void tile_gather(Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                            const typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    if (Sh::CPT % NT == 0 || q < Sh::CPT) {
+      const int r = q / Sh::CPR;
+      const int cc = q % Sh::CPR;
+#pragma unroll
+      for (int j = 0; j < Sh::CE; ++j) reg[i].e[j] = lds[r * Sh::PE + cc * Sh::CE + j];
+    }
+  }
+}
+
+// Registers (as tile_gather left them) -> the rows of tile y in HBM.
+template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
+__device__ __forceinline__ void tile_put(const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                         typename Bytes<S>::T* __restrict__ base,
+                                         uint64_t rowstride, uint32_t y) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<Sh::VB>::T V;
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    if (Sh::CPT % NT == 0 || q < Sh::CPT) {
+      const int r = q / Sh::CPR;
+      const int cc = q % Sh::CPR;
+      const uint64_t off = (uint64_t)r * rowstride + (uint64_t)y * Sh::R + (uint64_t)(cc * Sh::CE);
+      st_hint<H>(reinterpret_cast<V*>(base + off), reg[i].v);
+    }
+  }
+}
+
+// In place through one LDS tile: both tiles of the pair are read into
+// registers, then each in turn is scattered into LDS and gathered back in
+// destination order, and both are written.  Half the LDS of
+// tile_pair_inplace and twice the registers per thread, so that twice as
+// many pairs are in flight per compute unit.  Ends with the LDS free for the
+// next item only after the caller's barrier.
+template <int S, int B, bool VEC, int NT, int H = kHintPlain>
+__device__ __forceinline__ void tile_pair_inplace_rs(typename Bytes<S>::T* __restrict__ base,
+                                                     int m, uint32_t y,
+                                                     typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  const uint64_t rowstride = 1ull << (m + B);
+  const uint32_t yr = rev_bits(y, m);
+  const bool pal = (yr == y);
+  Chunk<S, Sh::VB> ra[PT], rb[PT];
+  tile_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
+  if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
+  tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+  __syncthreads();
+  tile_gather<S, B, VEC, NT, PT>(ra, lds);  // tile y, transposed: its rows go to yr
+  if (!pal) {
+    __syncthreads();
+    tile_scatter<S, B, VEC, NT, PT>(rb, lds);
+    __syncthreads();
+    tile_gather<S, B, VEC, NT, PT>(rb, lds);
+    tile_put<S, B, VEC, NT, PT, H>(rb, base, rowstride, y);
+  }
+  tile_put<S, B, VEC, NT, PT, H>(ra, base, rowstride, yr);
 }
 
 // In place: swap tiles y and yr = rev_m(y) of the array at `base` (one tile

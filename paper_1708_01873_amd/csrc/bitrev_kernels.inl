@@ -31,6 +31,28 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace(
   }
 }
 
+// In place, register-staged: as k_tile_inplace, with the pair held in
+// registers and transposed through a single LDS tile by half as many
+// threads (see tile_pair_inplace_rs).
+template <int S, int B, bool VEC, int H>
+__global__ __launch_bounds__((rs_threads<S, B, VEC>())) void k_tile_inplace_rs(
+    void* data, int m, uint64_t items_per_seg, uint64_t total_items, uint64_t seg_elems,
+    int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  constexpr int NT = rs_threads<S, B, VEC>();
+  __shared__ E lds[TileShape<S, B, VEC>::TILE_E];
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    uint64_t seg = 0, local = item;
+    if (items_per_seg != total_items) {
+      seg = item / items_per_seg;
+      local = item - seg * items_per_seg;
+    }
+    const uint32_t y = inplace_pair_at(m, local, balanced);
+    tile_pair_inplace_rs<S, B, VEC, NT, H>(static_cast<E*>(data) + seg * seg_elems, m, y, lds);
+    __syncthreads();
+  }
+}
+
 // Out of place: work item -> (array, tile y) -> tile rev_m(y) of dst.
 template <int S, int B, bool VEC, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace(
@@ -421,6 +443,23 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched_oop(
 
 template <int S, int B, bool VEC>
 hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
+  if (a.pipelined == 2) {
+    const int h = VEC ? a.hints : kHintPlain;
+    if (h == kHintStreamLoads) {
+      hipLaunchKernelGGL((k_tile_inplace_rs<S, B, VEC, kHintStreamLoads>), dim3(a.grid),
+                         dim3(rs_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
+                         a.total_items, a.seg_elems, a.balanced, a.xcds);
+    } else if (h == kHintStreamStores) {
+      hipLaunchKernelGGL((k_tile_inplace_rs<S, B, VEC, kHintStreamStores>), dim3(a.grid),
+                         dim3(rs_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
+                         a.total_items, a.seg_elems, a.balanced, a.xcds);
+    } else {
+      hipLaunchKernelGGL((k_tile_inplace_rs<S, B, VEC, kHintPlain>), dim3(a.grid),
+                         dim3(rs_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
+                         a.total_items, a.seg_elems, a.balanced, a.xcds);
+    }
+    return hipGetLastError();
+  }
   if (a.pipelined) {
     hipLaunchKernelGGL((k_tile_inplace_pipe<S, B, VEC>), dim3(a.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
@@ -447,7 +486,7 @@ hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
 
 template <int S, int B, bool VEC>
 hipError_t run_tile_outofplace(const TileLaunch& a, hipStream_t st) {
-  if (a.pipelined) {
+  if (a.pipelined == 1) {
     hipLaunchKernelGGL((k_tile_outofplace_pipe<S, B, VEC>), dim3(a.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
                        a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced, a.xcds);
@@ -657,6 +696,18 @@ hipError_t BITREV_CAT(launch_batched_s, BITREV_S)(const BatchedLaunch& a, hipStr
 }
 
 int BITREV_CAT(tile_threads_s, BITREV_S)(int b, bool vec) { return threads_for<BITREV_S>(b, vec); }
+
+template <int S, int B = 0>
+int rs_threads_for(int b, bool vec) {
+  if constexpr (B > max_tile_bits(S)) {
+    return 0;
+  } else {
+    if (b == B) return vec ? rs_threads<S, B, true>() : rs_threads<S, B, false>();
+    return rs_threads_for<S, B + 1>(b, vec);
+  }
+}
+
+int BITREV_CAT(tile_rs_threads_s, BITREV_S)(int b, bool vec) { return rs_threads_for<BITREV_S>(b, vec); }
 
 int BITREV_CAT(tile_occupancy_s, BITREV_S)(int b, bool vec, bool inplace, bool pipelined) {
   return occupancy_for<BITREV_S>(b, vec, inplace, pipelined);

@@ -27,7 +27,7 @@ struct TileLaunch {
   int balanced;             // work-item order: 0 natural, 1 balanced bit dealing
   int xcds;                 // number of XCDs the grid is dealt over
   uint32_t grid;            // workgroups (multiple of xcds)
-  int pipelined;            // 1: persistent software-pipelined kernel
+  int pipelined;            // 1: persistent software-pipelined, 2: register-staged (in place)
   int hints = 0;            // CacheHint of the one-item 16-byte kernels
 };
 
@@ -91,6 +91,7 @@ size_t tile_lds_bytes(int s, int b, bool inplace);
   hipError_t launch_evenodd_s##S(const void* src, void* dst, int k, uint64_t rows,   \
                                  uint32_t grid, hipStream_t st);                     \
   int tile_threads_s##S(int b, bool vec);                                            \
+  int tile_rs_threads_s##S(int b, bool vec);                                         \
   int tile_occupancy_s##S(int b, bool vec, bool inplace, bool pipelined);            \
   int batched_occupancy_s##S(int b, bool oop);                                     \
   int batched_threads_s##S(int b);

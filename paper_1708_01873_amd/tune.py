@@ -4,7 +4,8 @@ The tile width b is the method's one machine-dependent parameter: the paper
 notes that the buffered method's buffer size t = 2^(2b) has to be tuned per
 architecture (Introduction, matrix buffer; Results, where the buffer size was
 optimised per problem size).  On MI355X the kernel variant (one work item per
-workgroup, or persistent and software-pipelined), the work-item order and,
+workgroup, persistent and software-pipelined, or register-staged), the
+work-item order, the cache hints of the global accesses and,
 for the batched launch, the workgroups per compute unit matter as well.
 
 ``tune_plain`` and ``tune_batched`` time every candidate with HIP events on
@@ -109,10 +110,11 @@ def plain_candidates(log2n: int, elem_size: int, mode: int) -> list[Candidate]:
         if 2 * b > log2n or (elem_size << b) < 16:
             continue
         for order in (1, 2, 3):
-            for variant in (1, 2):
+            # variant 3 (register-staged) exists in place only
+            for variant in ((1, 2, 3) if mode == MODE_INPLACE else (1, 2)):
                 for xcd in (1, 2):
-                    # cache hints apply to the one-item kernels only
-                    for hints in ((1, 2, 3) if variant == 1 else (0,)):
+                    # cache hints apply to the one-item and register-staged kernels
+                    for hints in ((1, 2, 3) if variant != 2 else (0,)):
                         out.append(Candidate(b, order, variant, 0, xcd, hints))
     return out
 

@@ -89,7 +89,7 @@ def test_rows_validation(L):
 
 def test_config_validation(L):
     for cfg in (br.Config(8, 0, 0, 0), br.Config(-1, 0, 0, 0), br.Config(0, -5, 0, 0),
-                br.Config(0, 0, 4, 0), br.Config(0, 0, 0, 3), br.Config(0, 0, 0, -1),
+                br.Config(0, 0, 4, 0), br.Config(0, 0, 0, 4), br.Config(0, 0, 0, -1),
                 br.Config(0, 0, 0, 0, 3), br.Config(0, 0, 0, 0, 0, 4), br.Config(0, 0, 0, 0, 0, -1)):
         assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
 
@@ -174,6 +174,12 @@ def test_plan_query_defaults(L):
     assert 256 <= p["grid_blocks"] <= min(p["work_items"] + 7, 256 * 32)
     p = br.bitrev_plan_query(24, 8, variant=br.VARIANT_ONE_ITEM)
     assert p["variant"] == br.VARIANT_ONE_ITEM and p["grid_blocks"] >= p["work_items"]
+    # register-staged: half the threads and one LDS tile; out of place it is one-item
+    q = br.bitrev_plan_query(24, 8, variant=br.VARIANT_REGISTER_STAGED)
+    assert q["variant"] == 3 and q["block_threads"] == p["block_threads"] // 2
+    assert q["lds_bytes"] * 2 == p["lds_bytes"]
+    q = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE, variant=br.VARIANT_REGISTER_STAGED)
+    assert q["variant"] == br.VARIANT_ONE_ITEM
 
 
 def test_tuning_file(L, tmp_path):
@@ -190,7 +196,7 @@ def test_tuning_file(L, tmp_path):
         assert p["tile_bits"] == 4 and p["order"] == 1 and p["grid_blocks"] == 4 * 256
         for bad in ("inplace 8 24 6 0 2 0\n", "sideways 8 24 6 0 2 0 0\n",
                     "inplace 3 24 6 0 2 0 0\n", "inplace 8 24 9 0 2 0 0\n",
-                    "inplace 8 24 6 0 2 3 0\n", "inplace 8 24 6 0 2 0 3\n",
+                    "inplace 8 24 6 0 2 4 0\n", "inplace 8 24 6 0 2 0 3\n",
                     "inplace 8 24 6 0 2 0 0 7\n", "inplace 8 24 6 0 2 0 0 1 1\n",
                     "inplace 8 24 6 0 4 0 0\n"):
             f = tmp_path / "bad.txt"

@@ -67,7 +67,8 @@ def test_default_plan_every_k(s):
 @pytest.mark.parametrize("s", ELEM_SIZES)
 def test_forced_tile_widths(s):
     """Every compiled tile width b, at k = 2b (one tile), 2b + 1 (palindromic
-    pairs only), 2b + 3 and 2b + 6 (many pairs), both work orders."""
+    pairs only), 2b + 3 and 2b + 6 (many pairs), every work order and kernel
+    variant."""
     for b in range(1, MAX_B[s] + 1):
         for extra in (0, 1, 3, 6):
             k = 2 * b + extra
@@ -75,8 +76,8 @@ def test_forced_tile_widths(s):
                 continue
             host = workloads.byte_pattern((1 << k) * s, seed=7 * k + b)
             want = oracle.outofplace(host, s)
-            for order in (1, 2):
-                for variant in (1, 2):
+            for order in (1, 2, 3):
+                for variant in (1, 2, 3):
                     for inplace in (True, False):
                         got = _run(host, k, s, inplace, tile_bits=b, order=order,
                                    variant=variant)
@@ -98,22 +99,23 @@ def test_element_aligned_base(s):
 
 @pytest.mark.parametrize("s", ELEM_SIZES)
 def test_cache_hints(s):
-    """Every cache-hint instance of the one-item tile kernels (plain,
-    streaming loads, streaming stores), every order, in and out of place,
-    16-byte and per-element access, against the oracle."""
+    """Every cache-hint instance of the one-item tile kernels and of the
+    register-staged in-place kernel (plain, streaming loads, streaming
+    stores), every order, in and out of place, 16-byte and per-element
+    access, against the oracle."""
     for k in (13, 16):
         host = workloads.byte_pattern((1 << k) * s, seed=31 * s + k)
         want = oracle.outofplace(host, s)
         for hints in (br.HINTS_PLAIN, br.HINTS_STREAM_LOADS, br.HINTS_STREAM_STORES):
-            for inplace in (True, False):
+            for inplace, variant in ((True, 1), (True, 3), (False, 1)):
                 for order in (1, 2, 3):
                     for pad in (0, 1):
                         if pad and s >= 16:
                             continue
-                        got = _run(host, k, s, inplace, pad_front=pad, variant=1, order=order,
-                                   cache_hints=hints)
-                        assert_bytes_equal(got, want, "s=%d k=%d hints=%d ip=%s order=%d pad=%d"
-                                           % (s, k, hints, inplace, order, pad))
+                        got = _run(host, k, s, inplace, pad_front=pad, variant=variant,
+                                   order=order, cache_hints=hints)
+                        assert_bytes_equal(got, want, "s=%d k=%d hints=%d ip=%s v=%d order=%d "
+                                           "pad=%d" % (s, k, hints, inplace, variant, order, pad))
 
 
 def test_copy_hints():
@@ -135,7 +137,7 @@ def test_persistent_grid(grid):
     want = oracle.outofplace(host, s)
     for inplace in (True, False):
         for order in (1, 2):
-            for variant in (1, 2):
+            for variant in (1, 2, 3):
                 got = _run(host, k, s, inplace, grid_blocks=grid, order=order, variant=variant)
                 assert_bytes_equal(got, want, "grid=%d ip=%s order=%d variant=%d"
                                    % (grid, inplace, order, variant))
