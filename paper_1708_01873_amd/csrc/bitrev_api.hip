@@ -196,14 +196,17 @@ DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
   if (tiny && mode == 0) return {s >= 16 ? 5 : (s == 8 ? 5 : (s == 4 ? 6 : 7)), 2, 1, 2};
   if (tiny && mode == 1) return {s >= 8 ? 5 : (s == 4 ? 6 : 7), 2, s == 8 ? 3 : 2, 2};
   if (mode == 0) {  // in place
+    // the grouped order keeps runs of neighbouring tiles on both sides of
+    // each swap: complex64 2^24 +8%, float32 256 MiB +30%, complex128
+    // 64 MiB +13%, int16 +1%; where it measured slower (float32 up to
+    // 64 MiB, complex128 128-512 MiB: -3%) the balanced order stays
+    const bool mid = array_bytes > (64ull << 20);
     switch (s) {
       case 1: return {7, 1, 2, small ? 2 : 1};
-      case 2: return {7, 1, 2, small ? 2 : 1};
-      case 4: return small ? DefaultPlan{6, 2, 2, 1} : DefaultPlan{6, 1, 2, 1};
-      // 8 and 16 bytes: the grouped order keeps runs of neighbouring tiles
-      // on both sides of each swap (complex64 2^24: +8%, 2^26: +6%)
+      case 2: return {7, 1, 3, 2};
+      case 4: return mid ? DefaultPlan{6, 1, 3, 2} : DefaultPlan{6, 2, 2, 1};
       case 8: return {6, 1, 3, 2};
-      default: return small ? DefaultPlan{5, 1, 2, 2} : DefaultPlan{5, 1, 3, 2};
+      default: return (mid && small) ? DefaultPlan{5, 1, 2, 2} : DefaultPlan{5, 1, 3, 2};
     }
   }
   if (mode == 2) {  // batched (in place, persistent): complex64 measured on 4096 uneven arrays
