@@ -337,6 +337,9 @@ uint32_t bitrev_debug_digit_rev(uint32_t v, int j, int d);
 /* Number of y in [0, 2^m) with y <= drev(y), and the w-th such y. */
 uint64_t bitrev_debug_digit_pair_count(int m, int d);
 uint32_t bitrev_debug_digit_pair_at(int m, uint64_t w, int d);
+/* The w-th tile of the in-place digit kernels' order (grouped; the other
+ * tile of its pair is its digit reversal). */
+uint32_t bitrev_debug_digit_inplace_pair_at(int m, uint64_t w, int d);
 
 #ifdef __cplusplus
 }

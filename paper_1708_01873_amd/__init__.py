@@ -94,6 +94,7 @@ _SIGNATURES = {
     "bitrev_digitrev_outofplace": ([_VP, _VP, _I, _I, _SZ, _VP], _I),
     "bitrev_debug_digit_rev": ([ctypes.c_uint32, _I, _I], ctypes.c_uint32),
     "bitrev_debug_digit_pair_count": ([_I, _I], ctypes.c_uint64),
+    "bitrev_debug_digit_inplace_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
     "bitrev_debug_digit_pair_at": ([_I, ctypes.c_uint64, _I], ctypes.c_uint32),
     "bitrev_transpose_inplace": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_status_string": ([_I], ctypes.c_char_p),

@@ -671,6 +671,7 @@ bitrev_status_t run_digit(const void* src, void* dst, int k, int d, size_t s, vo
   a.balanced = 0;
   a.xcds = dp.xcd_remap == 2 ? 1 : dev.xcds;
   a.grid = default_grid(a.total_items, dev);
+  a.hints = default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, 1);
   a.pipelined = 0;
   const size_t vb = (s << b) < 16 ? (s << b) : 16;
   e = launch_digit((int)s, d, b, pointer_align(src, dst) % vb == 0, a, hs);
@@ -703,6 +704,11 @@ uint64_t bitrev_debug_digit_pair_count(int m, int d) {
 uint32_t bitrev_debug_digit_pair_at(int m, uint64_t w, int d) {
   if (m < 0 || m > 32 || d < 1 || d > 3 || m % d || w >= dpair_count(m, d)) return 0xFFFFFFFFu;
   return dpair_at(m, w, d);
+}
+
+uint32_t bitrev_debug_digit_inplace_pair_at(int m, uint64_t w, int d) {
+  if (m < 0 || m > 32 || d < 1 || d > 3 || m % d || w >= dpair_count(m, d)) return 0xFFFFFFFFu;
+  return dinplace_pair_at(m, w, d);
 }
 
 bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_size, void* stream) {

@@ -255,6 +255,57 @@ __host__ __device__ __forceinline__ uint32_t dpair_at(int m, uint64_t w, int d) 
   return y;
 }
 
+// Number of y with y < drev(y): (2^m - q^ceil(m/(2d))) / 2.  As for
+// pair_at, dpair_at lists exactly these first (w < dswap_pair_count).
+__host__ __device__ __forceinline__ uint64_t dswap_pair_count(int m, int d) {
+  const int digits = m / d;
+  return ((1ull << m) - (1ull << (d * ((digits + 1) / 2)))) >> 1;
+}
+
+// The t-th y with y = drev(y), 0 <= t < q^ceil(m/(2d)): the high digits
+// (and, for an odd digit count, the middle digit) come from t, the low
+// digits are the high ones in reverse order.
+__host__ __device__ __forceinline__ uint32_t dpalindrome_at(int m, uint32_t t, int d) {
+  const int digits = m / d;
+  const int h = digits / 2;
+  const uint32_t top = (digits & 1) ? t >> d : t;
+  const uint32_t mid = (digits & 1) ? t & ((1u << d) - 1u) : 0u;
+  return (top << (m - h * d)) | (mid << (h * d)) | drev_bits(top, h * d, d);
+}
+
+// The grouped order of group_pair_at with digits: y = [t | c | s], t and s
+// of j digits, drev(y) = [drev(s) | drev(c) | drev(t)]; a middle
+// c < drev(c) owns all (t, s), a digit palindrome c the pairs of the
+// 2j-digit [t|s] under its own digit reversal.  2jd <= m.
+__host__ __device__ __forceinline__ uint32_t dgroup_pair_at(int m, uint64_t w, int d, int j) {
+  const int gb = j * d;
+  const int mc = m - 2 * gb;
+  const uint64_t per = 1ull << (2 * gb);
+  const uint64_t r = dswap_pair_count(mc, d);
+  uint32_t c, z;
+  if (w < r * per) {
+    c = dpair_at(mc, w >> (2 * gb), d);
+    z = (uint32_t)(w & (per - 1));
+  } else {
+    const uint64_t w2 = w - r * per;
+    const uint64_t pp = dpair_count(2 * gb, d);
+    const uint64_t g = w2 / pp;
+    c = dpalindrome_at(mc, (uint32_t)g, d);
+    z = dpair_at(2 * gb, w2 - g * pp, d);
+  }
+  const uint32_t t = z >> gb, sb = z & ((1u << gb) - 1u);
+  return (t << (mc + gb)) | (c << gb) | sb;
+}
+
+// The digit kernels' in-place order: grouped with about 3 bits per side
+// (ceil(3 / d) digits), fewer where the middle is short, dpair_at's own
+// order when not even one digit per side fits.
+__host__ __device__ __forceinline__ uint32_t dinplace_pair_at(int m, uint64_t w, int d) {
+  int j = (3 + d - 1) / d;
+  if (2 * j * d > m) j = m / (2 * d);
+  return j ? dgroup_pair_at(m, w, d, j) : dpair_at(m, w, d);
+}
+
 // LDS padding per tile row, in elements: one element (at least 4 bytes)
 // staggers consecutive rows across banks for the column-wise scatter.
 __host__ __device__ constexpr int lds_pad_elems(int s) { return s >= 4 ? 1 : 4 / s; }

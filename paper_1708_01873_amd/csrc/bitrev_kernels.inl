@@ -283,7 +283,7 @@ hipError_t dispatch_dit(int b, bool vec, const DitLaunch& a, hipStream_t st) {
 // Digit reversal (radix-2^D digits), in place (src == dst: pairs
 // y <= drev(y)) or out of place; the tile width B and the middle width m are
 // whole numbers of digits, so drev([x | y | z]) = [drev(z) | drev(y) | drev(x)].
-template <int S, int B, int D, bool VEC>
+template <int S, int B, int D, bool VEC, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_digit(
     const void* src, void* dst, int m, uint64_t total_items, int xcds) {
   static_assert(B % D == 0, "the tile width must be a whole number of digits");
@@ -298,16 +298,17 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_digit(
   E* out = static_cast<E*>(dst);
   for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
     Chunk<S, Sh::VB> ra[PT], rb[PT];
-    const uint32_t y = inplace ? dpair_at(m, item, D) : (uint32_t)item;
+    const uint32_t y = inplace ? dinplace_pair_at(m, item, D) : (uint32_t)item;
     const uint32_t yr = drev_bits(y, m, D);
     const bool two = inplace && (y != yr);
-    tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
-    if (two) tile_load<S, B, VEC, NT, PT>(rb, in, rowstride, yr);
+    tile_load<S, B, VEC, NT, PT, H>(ra, in, rowstride, y);
+    if (two) tile_load<S, B, VEC, NT, PT, H>(rb, in, rowstride, yr);
     tile_scatter<S, B, VEC, NT, PT, D>(ra, lds);
     if (two) tile_scatter<S, B, VEC, NT, PT, D>(rb, lds + Sh::TILE_E);
     __syncthreads();
-    tile_store<S, B, VEC, NT, PT>(out, rowstride, yr, lds);
-    if (two) tile_store<S, B, VEC, NT, PT>(out, rowstride, y, lds + Sh::TILE_E);
+    // tile y first, then its partner, as in the bit-reversal kernels
+    if (two) tile_store<S, B, VEC, NT, PT, H>(out, rowstride, y, lds + Sh::TILE_E);
+    tile_store<S, B, VEC, NT, PT, H>(out, rowstride, yr, lds);
     __syncthreads();
   }
 }
@@ -579,11 +580,21 @@ hipError_t dispatch_digit(int b, bool vec, const TileLaunch& a, hipStream_t st) 
   } else {
     if (b == B) {
       if (vec) {
-        hipLaunchKernelGGL((k_tile_digit<S, B, D, true>), dim3(a.grid),
-                           dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
-                           a.total_items, a.xcds);
+        if (a.hints == kHintStreamLoads) {
+          hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintStreamLoads>), dim3(a.grid),
+                             dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
+                             a.total_items, a.xcds);
+        } else if (a.hints == kHintStreamStores) {
+          hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintStreamStores>), dim3(a.grid),
+                             dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
+                             a.total_items, a.xcds);
+        } else {
+          hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintPlain>), dim3(a.grid),
+                             dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
+                             a.total_items, a.xcds);
+        }
       } else {
-        hipLaunchKernelGGL((k_tile_digit<S, B, D, false>), dim3(a.grid),
+        hipLaunchKernelGGL((k_tile_digit<S, B, D, false, kHintPlain>), dim3(a.grid),
                            dim3(tile_threads<S, B, false>()), 0, st, a.src, a.dst, a.m,
                            a.total_items, a.xcds);
       }

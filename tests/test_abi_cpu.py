@@ -346,6 +346,20 @@ def test_digit_pair_enumeration(L, d):
             assert L.bitrev_debug_digit_rev(v, m, d) == oracle.digit_rev(v, m, d)
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_digit_inplace_order_covers_every_pair_once(L, d):
+    """The in-place digit kernels' grouped order names each pair
+    {y, drev(y)} exactly once, for every middle width."""
+    for m in range(0, 19, d):
+        count = L.bitrev_debug_digit_pair_count(m, d)
+        ys = np.array([L.bitrev_debug_digit_inplace_pair_at(m, w, d) for w in range(count)],
+                      dtype=np.int64)
+        dr = np.array([oracle.digit_rev(int(y), m, d) for y in ys], dtype=np.int64)
+        assert np.all(ys < 2**m), (m, d)
+        assert len(np.unique(np.minimum(ys, dr))) == count, (m, d)
+        assert L.bitrev_debug_digit_inplace_pair_at(m, count, d) == 0xFFFFFFFF
+
+
 def test_digitrev_validation(L):
     assert L.bitrev_digitrev_inplace(FAKE, 25, 2, 8, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_digitrev_inplace(FAKE, 24, 4, 8, None) == br.ERROR_INVALID_VALUE

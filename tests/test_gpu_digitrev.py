@@ -32,14 +32,18 @@ def test_digitrev_every_k(s, d):
 
 
 def test_digitrev_complex64_2p24():
-    host = workloads.complex64_normal(24, workloads.SEEDS["c2"])
-    for d in (2, 3):
-        want = oracle.digit_outofplace(host, d)
-        x = torch.from_numpy(host).cuda()
-        y = br.bitrev_digitrev_outofplace(x, None, d)
-        assert_bytes_equal(to_host_bytes(y), want, "c2 digits d=%d oop" % d)
-        br.bitrev_digitrev_inplace(x, d)
-        assert_bytes_equal(to_host_bytes(x), want, "c2 digits d=%d ip" % d)
+    """Full-size arrays, where the plans take the streaming cache hints:
+    complex64 128 MiB (loads out of place, stores in place) and float32
+    64 MiB (loads in and out of place)."""
+    for name, host, s in (("c64", workloads.complex64_normal(24, workloads.SEEDS["c2"]), 8),
+                          ("f32", workloads.byte_pattern((1 << 24) * 4, seed=44), 4)):
+        for d in (2, 3):
+            want = oracle.digit_outofplace(host, d, s)
+            x = to_device(host, s)
+            y = br.bitrev_digitrev_outofplace(x, None, d)
+            assert_bytes_equal(to_host_bytes(y), want, "%s digits d=%d oop" % (name, d))
+            br.bitrev_digitrev_inplace(x, d)
+            assert_bytes_equal(to_host_bytes(x), want, "%s digits d=%d ip" % (name, d))
 
 
 def test_digitrev_misaligned_and_errors():
