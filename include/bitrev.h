@@ -67,10 +67,12 @@ typedef struct bitrev_config {
                     * work items with a grid stride (persistent); 0 = choose */
   int order;       /* work-item order: 0 = choose, 1 = natural, 2 = balanced
                     * bit dealing (spreads tile rows over HBM channels),
-                    * 3 = grouped (in place: the pairs of 2^3 x 2^3 tiles that
-                    * share their middle bits run together, so both sides of
-                    * the swaps touch runs of neighbouring tiles; out of
-                    * place it is the balanced order) */
+                    * 3 = grouped (the tile index y = [t | c | s] with t and
+                    * s of 3 bits: in place, the pairs of the 64 tiles that
+                    * share their middle bits c run together; out of place,
+                    * (t, s) vary fastest and c is dealt as in the balanced
+                    * order; either way both sides of the permutation touch
+                    * runs of neighbouring tiles) */
   int variant;     /* tile kernel: 0 = choose, 1 = one work item per
                     * workgroup, 2 = persistent and software-pipelined (each
                     * workgroup loads its next tiles while storing the
@@ -85,8 +87,11 @@ typedef struct bitrev_config {
                     * robin), 2 = leave the dispatch order as is */
   int cache_hints; /* tile kernels' global accesses: 0 = choose, 1 = plain,
                     * 2 = streaming (non-temporal) loads, 3 = streaming
-                    * stores; applies to one-item-per-workgroup tile kernels
-                    * with 16-byte accesses, otherwise plain */
+                    * stores; applies to the one-item and register-staged
+                    * tile kernels with 16-byte accesses, otherwise plain.
+                    * The choice: streaming loads beyond 32 MiB out of place
+                    * and beyond 64 MiB in place, except 8-byte elements in
+                    * place up to 256 MiB, which take streaming stores */
 } bitrev_config_t;
 
 /* Which code path and geometry a call uses (bitrev_plan_query). */
