@@ -264,7 +264,9 @@ int threads_of(int s, int b, bool vec) {
 // The kernels' order code (bit 0 balanced, bits 1.. group width) for a
 // plan's order: 1 natural, 2 balanced, 3 grouped.
 int order_code(int order) {
-  if (order == 3) return 1 | (BITREV_GROUP_J << 1);  // the kernels clamp j to m / 2
+  // grouped: groups in pair_at's natural order (measured 1% ahead of the
+  // balanced group order for complex64 2^24-2^26); the kernels clamp j
+  if (order == 3) return BITREV_GROUP_J << 1;
   return order == 2 ? 1 : 0;
 }
 
