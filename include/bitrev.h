@@ -276,6 +276,13 @@ bitrev_status_t bitrev_digitrev_outofplace(const void* src, void* dst, int log2n
  * twiddles rounded once from double precision. */
 bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t rows, int stages,
                                   int inverse, int dtype, void* stream);
+/* The same with a launch configuration: tile_bits (>= stages; the default
+ * is the plain kernel's width, at least stages), order, grid_blocks,
+ * xcd_remap and cache_hints as in bitrev_config_t; variant is ignored (one
+ * work item per workgroup). */
+bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int64_t rows,
+                                     int stages, int inverse, int dtype,
+                                     const bitrev_config_t* cfg, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* The paper's recursive scheme, as an A/B baseline for the one-pass kernels */

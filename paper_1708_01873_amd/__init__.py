@@ -87,6 +87,7 @@ _SIGNATURES = {
     "bitrev_copy_ex": ([_VP, _VP, _SZ, _I, _VP], _I),
     "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
     "bitrev_dit_stages": ([_VP, _VP, _I, _I64, _I, _I, _I, _VP], _I),
+    "bitrev_dit_stages_ex": ([_VP, _VP, _I, _I64, _I, _I, _I, _CFGP, _VP], _I),
     "bitrev_digitrev_inplace": ([_VP, _I, _I, _SZ, _VP], _I),
     "bitrev_rows_strided": ([_VP, _VP, _I, _I64, _I64, _I64, _SZ, _VP], _I),
     "bitrev_evenodd": ([_VP, _VP, _I, _I64, _SZ, _VP], _I),
@@ -395,7 +396,8 @@ def bitrev_digitrev_outofplace(src, dst=None, digit_bits: int = 2, log2n: Option
 
 
 def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, log2n=None,
-                      stream=None):
+                      tile_bits=0, grid_blocks=0, order=0, xcd_remap=0, cache_hints=0,
+                      config=None, stream=None):
     """Bit reversal of each row (last dimension, complex64 or complex128)
     followed by the first `stages` radix-2 DIT FFT levels; ``dst is src``
     works in place.  Allocates ``dst`` when not given."""
@@ -413,8 +415,9 @@ def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, 
     if rows << k != src.numel():
         raise ValueError("not a whole number of rows")
     dtype = 0 if src.dtype == torch.complex64 else 1
-    _check(_load().bitrev_dit_stages(sp, dp, k, rows, int(stages), 1 if inverse else 0, dtype,
-                                     _stream(stream)), "bitrev_dit_stages")
+    cfg = _config(tile_bits, grid_blocks, order, config, 0, xcd_remap, cache_hints)
+    _check(_load().bitrev_dit_stages_ex(sp, dp, k, rows, int(stages), 1 if inverse else 0, dtype,
+                                        cfg, _stream(stream)), "bitrev_dit_stages")
     return dst
 
 

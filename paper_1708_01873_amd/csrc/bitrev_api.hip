@@ -721,11 +721,13 @@ bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_s
   return run_transpose(data, log2side, elem_size, static_cast<hipStream_t>(stream));
 }
 
-bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t rows, int stages,
-                                  int inverse, int dtype, void* stream) {
+bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int64_t rows,
+                                     int stages, int inverse, int dtype,
+                                     const bitrev_config_t* cfg, void* stream) {
   // ---- validation: no HIP call before this block completes ----
   if (src == NULL || dst == NULL || log2n < 0 || log2n > BITREV_MAX_LOG2N || rows < 0 ||
-      stages < 0 || stages > 7 || (inverse != 0 && inverse != 1) || (dtype != 0 && dtype != 1))
+      stages < 0 || stages > 7 || (inverse != 0 && inverse != 1) || (dtype != 0 && dtype != 1) ||
+      !valid_config(cfg))
     return BITREV_ERROR_INVALID_VALUE;
   const size_t s = dtype == 0 ? 8 : 16;
   if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % s)
@@ -735,17 +737,26 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
   const bool inplace = (src == dst);
   if (!inplace && overlap(src, dst, (size_t)(n * s * (uint64_t)rows))) return BITREV_ERROR_ALIAS;
   if (2 * stages > log2n || stages > max_tile_bits((int)s)) return BITREV_ERROR_NOT_SUPPORTED;
-  if (stages == 0) return run_plain(src, dst, log2n, rows, s, NULL, stream);
+  if (stages == 0) return run_plain(src, dst, log2n, rows, s, cfg, stream);
   if (rows == 0) return BITREV_SUCCESS;
   // ---- plan and launch ----
   DeviceInfo d;
   bitrev_status_t st = device_info(&d, false);
   if (st != BITREV_SUCCESS) return st;
   const DefaultPlan dp = default_plan(inplace ? 0 : 1, (int)s, n * s);
-  int b = dp.b;
-  if (b < stages) b = stages;
-  if (b > max_tile_bits((int)s)) b = max_tile_bits((int)s);
-  if (2 * b > log2n) b = log2n / 2;
+  int b;
+  if (cfg && cfg->tile_bits) {
+    b = cfg->tile_bits;  // forced: must hold the levels and fit
+    if (2 * b > log2n || b > max_tile_bits((int)s)) return BITREV_ERROR_NOT_SUPPORTED;
+  } else {
+    // in place, complex64 takes b = 5 where the levels fit: the LDS passes
+    // over a pair of 2^6-row tiles held two workgroups per CU
+    // (complex64 2^24, 3-5 levels: 4864-5159 -> 5565-5717 GB/s)
+    b = (inplace && s == 8) ? 5 : dp.b;
+    if (b < stages) b = stages;
+    if (b > max_tile_bits((int)s)) b = max_tile_bits((int)s);
+    if (2 * b > log2n) b = log2n / 2;
+  }
   const size_t lds = tile_lds_bytes_for((int)s, b, 2) + ((size_t)1 << b) * (s / 2);
   if (b < stages || lds > d.lds_per_block) return BITREV_ERROR_NOT_SUPPORTED;
   const int m = log2n - 2 * b;
@@ -757,11 +768,17 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
   a.t.items_per_seg = inplace ? pair_count(m) : (1ull << m);
   a.t.total_items = a.t.items_per_seg * (uint64_t)rows;
   a.t.seg_elems = n;
-  a.t.balanced = order_code(inplace ? 3 : 2);  // grouped pairs in place, balanced tiles out of place
-  a.t.xcds = dp.xcd_remap == 2 ? 1 : d.xcds;  // the plain kernel's choice for this size
-  a.t.grid = default_grid(a.t.total_items, d);
+  // grouped pairs in place, balanced tiles out of place; the XCD mapping and
+  // cache hints of the plain kernel for this size
+  a.t.balanced = order_code((cfg && cfg->order) ? cfg->order : (inplace ? 3 : 2));
+  const int xr = (cfg && cfg->xcd_remap) ? cfg->xcd_remap : dp.xcd_remap;
+  a.t.xcds = xr == 2 ? 1 : d.xcds;
+  a.t.grid = (cfg && cfg->grid_blocks > 0) ? round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds)
+                                           : default_grid(a.t.total_items, d);
   a.t.pipelined = 0;
-  a.t.hints = default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, rows);
+  a.t.hints = (cfg && cfg->cache_hints)
+                  ? cfg->cache_hints - 1
+                  : default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, rows);
   a.stages = stages;
   a.inverse = inverse;
   const size_t vb = (s << b) < 16 ? (s << b) : 16;
@@ -769,6 +786,11 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
   const hipError_t e = s == 8 ? launch_dit_s8(b, vec, a, static_cast<hipStream_t>(stream))
                               : launch_dit_s16(b, vec, a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t rows, int stages,
+                                  int inverse, int dtype, void* stream) {
+  return bitrev_dit_stages_ex(src, dst, log2n, rows, stages, inverse, dtype, NULL, stream);
 }
 
 bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size, void* stream) {

@@ -58,6 +58,21 @@ def test_dit_stages_sweep(dtype):
                 _check(to_host_bytes(t).view(dtype), x, L, inverse, dtype)
 
 
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_dit_forced_tile_widths(dtype):
+    """Every tile width that holds the levels, in and out of place, through
+    the configured entry point."""
+    k = 14
+    for L in range(1, 7):
+        for b in range(L, 7 if k >= 12 else k // 2 + 1):
+            x = _data(k, 1, dtype, 100 * L + b)
+            t = torch.from_numpy(x).cuda()
+            y = br.bitrev_dit_stages(t, stages=L, tile_bits=b)
+            _check(to_host_bytes(y).view(dtype), x, L, False, dtype)
+            br.bitrev_dit_stages(t, t, stages=L, tile_bits=b, order=br.ORDER_BALANCED)
+            _check(to_host_bytes(t).view(dtype), x, L, False, dtype)
+
+
 def test_dit_rows_and_full_size():
     """Many rows, and the complex64 2^24 array at six fused levels."""
     x = _data(12, 9, np.complex64, 3).reshape(9, 1 << 12)
