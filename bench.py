@@ -105,6 +105,18 @@ def read_traffic(kernel: str):
         return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(host, target_s: float = 10.0, max_reps: int = 20):
     """The oracle's in-place permutation of the same array on one host core,
     repeated until about target_s seconds have run."""
@@ -402,6 +414,8 @@ def main() -> int:
             "kind": "oracle",
             "sample": "the full 2^24 complex64 array, in place, %d repetitions in %.1f s" % (reps, el),
             "bit_exact_vs_oracle_outofplace": ok,
+            "cpu_model": cpu_model(),
+            "host_cores_available": len(os.sched_getaffinity(0)),
         }
     print(json.dumps(out), flush=True)
     return 0
