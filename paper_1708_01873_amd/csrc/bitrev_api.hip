@@ -177,13 +177,14 @@ enum { kModeInplace = 0, kModeOutofplace = 1, kModeBatched = 2 };
 // Built-in plan per (mode, element size, array bytes), from sweeps of tile
 // width x work order x kernel variant x XCD renumbering on MI355X with the
 // caches evicted before each call (arrays of 8 MiB to 4 GiB); each entry is
-// the one closest to the best at every measured size of its class.  Rows of 2^b * s >= 128
-// bytes keep every HBM access a run of whole 128-byte lines.  "small" arrays
-// (<= 512 MiB) interact with the 256 MiB Infinity Cache and favour different
-// choices than arrays far beyond it.
+// the one closest to the best at every measured size of its class.  Rows of
+// 2^b * s >= 128 bytes keep every HBM access a run of whole 128-byte lines.
+// "small" arrays (<= 512 MiB) interact with the 256 MiB Infinity Cache and
+// favour different choices than arrays far beyond it.  The cache hints are
+// chosen separately (default_hints).
 struct DefaultPlan {
   int b;
-  int variant;   // 1 one item per workgroup, 2 persistent pipelined
+  int variant;   // 1 one item per workgroup, 2 persistent pipelined, 3 register-staged
   int order;     // 1 natural, 2 balanced, 3 grouped
   int xcd_remap; // 1 contiguous ranges per XCD, 2 dispatch order
 };
