@@ -214,6 +214,22 @@ bitrev_status_t bitrev_inplace_ex(void* data, int log2n, size_t elem_size,
                                   const bitrev_config_t* cfg, void* stream);
 bitrev_status_t bitrev_outofplace_ex(const void* src, void* dst, int log2n, size_t elem_size,
                                      const bitrev_config_t* cfg, void* stream);
+/* Kernel timing for measurement: as bitrev_inplace_ex / bitrev_outofplace_ex,
+ * and the launch of the call's one kernel records start_event as the kernel
+ * starts and stop_event as it ends (hipExtLaunchKernel), so that
+ * hipEventElapsedTime between them is the kernel's own duration, without the
+ * dispatch latency that events recorded on the stream around the call also
+ * include.  Both events are the caller's (hipEvent_t created with timing
+ * enabled); both must be given (else BITREV_ERROR_INVALID_VALUE).  Where the
+ * call runs no kernel the events are recorded back to back.  This launch path
+ * adds dispatch latency on the stream (about 9 us measured on MI355X), so it
+ * times the kernel, not the throughput of a sequence of calls. */
+bitrev_status_t bitrev_inplace_timed(void* data, int log2n, size_t elem_size,
+                                     const bitrev_config_t* cfg, void* start_event,
+                                     void* stop_event, void* stream);
+bitrev_status_t bitrev_outofplace_timed(const void* src, void* dst, int log2n, size_t elem_size,
+                                        const bitrev_config_t* cfg, void* start_event,
+                                        void* stop_event, void* stream);
 bitrev_status_t bitrev_rows_ex(const void* src, void* dst, int log2n, int64_t rows,
                                size_t elem_size, const bitrev_config_t* cfg, void* stream);
 bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t* offsets,

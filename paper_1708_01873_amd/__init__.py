@@ -78,6 +78,8 @@ _SIGNATURES = {
     "bitrev_batched_errors": ([_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _VP], _I),
     "bitrev_inplace_ex": ([_VP, _I, _SZ, _CFGP, _VP], _I),
     "bitrev_outofplace_ex": ([_VP, _VP, _I, _SZ, _CFGP, _VP], _I),
+    "bitrev_inplace_timed": ([_VP, _I, _SZ, _CFGP, _VP, _VP, _VP], _I),
+    "bitrev_outofplace_timed": ([_VP, _VP, _I, _SZ, _CFGP, _VP, _VP, _VP], _I),
     "bitrev_rows_ex": ([_VP, _VP, _I, _I64, _SZ, _CFGP, _VP], _I),
     "bitrev_batched_ex": ([_VP, _I64, _VP, _VP, _I64, _SZ, _VP, _SZ, _CFGP, _VP], _I),
     "bitrev_plan_query": ([_I, _SZ, _I64, _I, _CFGP, ctypes.POINTER(Plan)], _I),
@@ -197,6 +199,29 @@ def bitrev_inplace(data, log2n: Optional[int] = None, *, tile_bits=0, grid_block
     else:
         _check(L.bitrev_inplace_ex(ptr, k, s, ctypes.byref(cfg), _stream(stream)),
                "bitrev_inplace_ex")
+    return data
+
+
+def _event_handle(event, name):
+    handle = getattr(event, "cuda_event", 0)
+    if not handle:
+        raise ValueError("%s must be a torch.cuda.Event(enable_timing=True) that has been "
+                         "recorded once (torch creates the HIP event on its first record)" % name)
+    return ctypes.c_void_p(handle)
+
+
+def bitrev_inplace_timed(data, start_event, stop_event, log2n: Optional[int] = None, *,
+                         tile_bits=0, grid_blocks=0, order=0, variant=0, xcd_remap=0,
+                         cache_hints=0, config=None, stream=None):
+    """bitrev_inplace whose kernel launch records ``start_event`` as the
+    kernel starts and ``stop_event`` as it ends, so that
+    ``start_event.elapsed_time(stop_event)`` is the kernel's own duration."""
+    ptr, s = _tensor_args(data, "data")
+    k = _log2_exact(data.numel()) if log2n is None else int(log2n)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
+    _check(_load().bitrev_inplace_timed(ptr, k, s, cfg, _event_handle(start_event, "start_event"),
+                                        _event_handle(stop_event, "stop_event"), _stream(stream)),
+           "bitrev_inplace_timed")
     return data
 
 
@@ -468,7 +493,7 @@ def bitrev_tuning_format() -> str:
 
 
 __all__ = [
-    "BitrevError", "Config", "Plan", "lib", "abi_version", "status_string",
+    "BitrevError", "Config", "Plan", "lib", "abi_version", "status_string", "bitrev_inplace_timed",
     "bitrev_inplace", "bitrev_outofplace", "bitrev_rows", "bitrev_batched",
     "bitrev_batched_workspace_size", "bitrev_batched_errors", "bitrev_copy",
     "bitrev_plan_query", "bitrev_load_tuning", "bitrev_tuning_format",

@@ -448,8 +448,10 @@ bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo
 // ---------------------------------------------------------------------------
 hipError_t launch_tile(bool inplace, int s, const Plan& p, const void* src, void* dst,
                        uint64_t src_stride, uint64_t dst_stride, const DeviceInfo& d,
-                       hipStream_t st) {
+                       hipStream_t st, void* ev_start = nullptr, void* ev_stop = nullptr) {
   TileLaunch a;
+  a.ev_start = ev_start;
+  a.ev_stop = ev_stop;
   a.src = src;
   a.dst = dst;
   a.m = p.m;
@@ -522,9 +524,12 @@ bool ranges_overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbyt
 
 // Common body of the plain, rows and strided entry points.  Strides are in
 // elements between consecutive arrays; 0 means 2^k (contiguous rows).
+// ev_start / ev_stop: optional hipEvent_t recorded as the path's one kernel
+// starts and ends (around the launch where the path is not a tile kernel).
 bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_t s,
                           const bitrev_config_t* cfg, void* stream, uint64_t src_stride = 0,
-                          uint64_t dst_stride = 0) {
+                          uint64_t dst_stride = 0, void* ev_start = nullptr,
+                          void* ev_stop = nullptr) {
   // ---- validation: no HIP call before this block completes ----
   if (src == NULL || dst == NULL) return BITREV_ERROR_INVALID_VALUE;
   if (k < 0 || k > BITREV_MAX_LOG2N || !valid_elem_size(s) || rows < 0 || !valid_config(cfg))
@@ -544,7 +549,14 @@ bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_
   if (!inplace && ranges_overlap(src, footprint(n, rows, src_stride, s), dst,
                                  footprint(n, rows, dst_stride, s)))
     return BITREV_ERROR_ALIAS;
-  if (rows == 0 || (inplace && k <= 1)) return BITREV_SUCCESS;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const bool timed = ev_start != nullptr && ev_stop != nullptr;
+  if (rows == 0 || (inplace && k <= 1)) {
+    if (!timed) return BITREV_SUCCESS;  // nothing to run: the events bracket nothing
+    hipError_t e = hipEventRecord(static_cast<hipEvent_t>(ev_start), hs);
+    if (e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(ev_stop), hs);
+    return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+  }
   // ---- plan and launch ----
   DeviceInfo d;
   bitrev_status_t st = device_info(&d, false);
@@ -559,12 +571,14 @@ bitrev_status_t run_plain(const void* src, void* dst, int k, int64_t rows, size_
   st = plan_plain(inplace ? kModeInplace : kModeOutofplace, k, (int)s, rows, cfg, align, d, true,
                   &p);
   if (st != BITREV_SUCCESS) return st;
-  hipStream_t hs = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (p.path == BITREV_PATH_WAVE) {
-    e = launch_wave((int)s, p, src, dst, k, rows, src_stride, dst_stride, hs);
+    if (timed) e = hipEventRecord(static_cast<hipEvent_t>(ev_start), hs);
+    if (e == hipSuccess) e = launch_wave((int)s, p, src, dst, k, rows, src_stride, dst_stride, hs);
+    if (timed && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(ev_stop), hs);
   } else if (p.path == BITREV_PATH_TILE) {
-    e = launch_tile(inplace, (int)s, p, src, dst, src_stride, dst_stride, d, hs);
+    e = launch_tile(inplace, (int)s, p, src, dst, src_stride, dst_stride, d, hs,
+                    timed ? ev_start : nullptr, timed ? ev_stop : nullptr);
   }
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
 }
@@ -815,6 +829,20 @@ bitrev_status_t bitrev_inplace(void* data, int log2n, size_t elem_size, void* st
 bitrev_status_t bitrev_inplace_ex(void* data, int log2n, size_t elem_size,
                                   const bitrev_config_t* cfg, void* stream) {
   return run_plain(data, data, log2n, 1, elem_size, cfg, stream);
+}
+
+bitrev_status_t bitrev_inplace_timed(void* data, int log2n, size_t elem_size,
+                                     const bitrev_config_t* cfg, void* start_event,
+                                     void* stop_event, void* stream) {
+  if (start_event == NULL || stop_event == NULL) return BITREV_ERROR_INVALID_VALUE;
+  return run_plain(data, data, log2n, 1, elem_size, cfg, stream, 0, 0, start_event, stop_event);
+}
+
+bitrev_status_t bitrev_outofplace_timed(const void* src, void* dst, int log2n, size_t elem_size,
+                                        const bitrev_config_t* cfg, void* start_event,
+                                        void* stop_event, void* stream) {
+  if (start_event == NULL || stop_event == NULL) return BITREV_ERROR_INVALID_VALUE;
+  return run_plain(src, dst, log2n, 1, elem_size, cfg, stream, 0, 0, start_event, stop_event);
 }
 
 bitrev_status_t bitrev_outofplace(const void* src, void* dst, int log2n, size_t elem_size,

@@ -1,5 +1,7 @@
 // Kernels of libbitrev, instantiated for one element size BITREV_S per
 // translation unit (bitrev_s<S>.hip includes this file).
+#include <hip/hip_ext.h>
+
 #include "bitrev_device.hpp"
 #include "bitrev_launch.hpp"
 
@@ -9,6 +11,16 @@
 
 namespace bitrev {
 namespace {
+
+// Launch `kernel`; non-null events are recorded by the dispatch itself as
+// the kernel starts and ends, so that they time the kernel alone.
+template <typename F, typename... Args>
+hipError_t launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t st, void* ev_start,
+                        void* ev_stop, Args... args) {
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, st, static_cast<hipEvent_t>(ev_start),
+                        static_cast<hipEvent_t>(ev_stop), 0, args...);
+  return hipGetLastError();
+}
 
 // In place, one array or `total_items / items_per_seg` equal arrays: work
 // item -> (array, pair y <= rev_m(y)) -> swap the two tiles through LDS.
@@ -442,75 +454,49 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched_oop(
   }
 }
 
+template <int S, int B, bool VEC, int H>
+hipError_t run_inplace_h(const TileLaunch& a, hipStream_t st) {
+  if (a.pipelined == 2)
+    return launch_timed((k_tile_inplace_rs<S, B, VEC, H>), dim3(a.grid),
+                        dim3(rs_threads<S, B, VEC>()), st, a.ev_start, a.ev_stop, a.dst, a.m,
+                        a.items_per_seg, a.total_items, a.seg_elems, a.balanced, a.xcds);
+  return launch_timed((k_tile_inplace<S, B, VEC, H>), dim3(a.grid),
+                      dim3(tile_threads<S, B, VEC>()), st, a.ev_start, a.ev_stop, a.dst, a.m,
+                      a.items_per_seg, a.total_items, a.seg_elems, a.balanced, a.xcds);
+}
+
 template <int S, int B, bool VEC>
 hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
-  if (a.pipelined == 2) {
-    const int h = VEC ? a.hints : kHintPlain;
-    if (h == kHintStreamLoads) {
-      hipLaunchKernelGGL((k_tile_inplace_rs<S, B, VEC, kHintStreamLoads>), dim3(a.grid),
-                         dim3(rs_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
-                         a.total_items, a.seg_elems, a.balanced, a.xcds);
-    } else if (h == kHintStreamStores) {
-      hipLaunchKernelGGL((k_tile_inplace_rs<S, B, VEC, kHintStreamStores>), dim3(a.grid),
-                         dim3(rs_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
-                         a.total_items, a.seg_elems, a.balanced, a.xcds);
-    } else {
-      hipLaunchKernelGGL((k_tile_inplace_rs<S, B, VEC, kHintPlain>), dim3(a.grid),
-                         dim3(rs_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
-                         a.total_items, a.seg_elems, a.balanced, a.xcds);
-    }
-    return hipGetLastError();
-  }
-  if (a.pipelined) {
-    hipLaunchKernelGGL((k_tile_inplace_pipe<S, B, VEC>), dim3(a.grid),
-                       dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
-                       a.total_items, a.seg_elems, a.balanced, a.xcds);
-  } else {
-    // cache hints only on the 16-byte form; the per-element form stays plain
-    const int h = VEC ? a.hints : kHintPlain;
-    if (h == kHintStreamLoads) {
-      hipLaunchKernelGGL((k_tile_inplace<S, B, VEC, kHintStreamLoads>), dim3(a.grid),
-                         dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
-                         a.total_items, a.seg_elems, a.balanced, a.xcds);
-    } else if (h == kHintStreamStores) {
-      hipLaunchKernelGGL((k_tile_inplace<S, B, VEC, kHintStreamStores>), dim3(a.grid),
-                         dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
-                         a.total_items, a.seg_elems, a.balanced, a.xcds);
-    } else {
-      hipLaunchKernelGGL((k_tile_inplace<S, B, VEC, kHintPlain>), dim3(a.grid),
-                         dim3(tile_threads<S, B, VEC>()), 0, st, a.dst, a.m, a.items_per_seg,
-                         a.total_items, a.seg_elems, a.balanced, a.xcds);
-    }
-  }
-  return hipGetLastError();
+  if (a.pipelined == 1)
+    return launch_timed((k_tile_inplace_pipe<S, B, VEC>), dim3(a.grid),
+                        dim3(tile_threads<S, B, VEC>()), st, a.ev_start, a.ev_stop, a.dst, a.m,
+                        a.items_per_seg, a.total_items, a.seg_elems, a.balanced, a.xcds);
+  // cache hints only on the 16-byte form; the per-element form stays plain
+  const int h = VEC ? a.hints : kHintPlain;
+  if (h == kHintStreamLoads) return run_inplace_h<S, B, VEC, kHintStreamLoads>(a, st);
+  if (h == kHintStreamStores) return run_inplace_h<S, B, VEC, kHintStreamStores>(a, st);
+  return run_inplace_h<S, B, VEC, kHintPlain>(a, st);
+}
+
+template <int S, int B, bool VEC, int H>
+hipError_t run_outofplace_h(const TileLaunch& a, hipStream_t st) {
+  return launch_timed((k_tile_outofplace<S, B, VEC, H>), dim3(a.grid),
+                      dim3(tile_threads<S, B, VEC>()), st, a.ev_start, a.ev_stop, a.src, a.dst,
+                      a.m, a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems,
+                      a.balanced, a.xcds);
 }
 
 template <int S, int B, bool VEC>
 hipError_t run_tile_outofplace(const TileLaunch& a, hipStream_t st) {
-  if (a.pipelined == 1) {
-    hipLaunchKernelGGL((k_tile_outofplace_pipe<S, B, VEC>), dim3(a.grid),
-                       dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m, a.items_per_seg,
-                       a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced, a.xcds);
-  } else {
-    const int h = VEC ? a.hints : kHintPlain;
-    if (h == kHintStreamLoads) {
-      hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC, kHintStreamLoads>), dim3(a.grid),
-                         dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m,
-                         a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced,
-                         a.xcds);
-    } else if (h == kHintStreamStores) {
-      hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC, kHintStreamStores>), dim3(a.grid),
-                         dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m,
-                         a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced,
-                         a.xcds);
-    } else {
-      hipLaunchKernelGGL((k_tile_outofplace<S, B, VEC, kHintPlain>), dim3(a.grid),
-                         dim3(tile_threads<S, B, VEC>()), 0, st, a.src, a.dst, a.m,
-                         a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems, a.balanced,
-                         a.xcds);
-    }
-  }
-  return hipGetLastError();
+  if (a.pipelined == 1)
+    return launch_timed((k_tile_outofplace_pipe<S, B, VEC>), dim3(a.grid),
+                        dim3(tile_threads<S, B, VEC>()), st, a.ev_start, a.ev_stop, a.src, a.dst,
+                        a.m, a.items_per_seg, a.total_items, a.seg_elems, a.dst_seg_elems,
+                        a.balanced, a.xcds);
+  const int h = VEC ? a.hints : kHintPlain;
+  if (h == kHintStreamLoads) return run_outofplace_h<S, B, VEC, kHintStreamLoads>(a, st);
+  if (h == kHintStreamStores) return run_outofplace_h<S, B, VEC, kHintStreamStores>(a, st);
+  return run_outofplace_h<S, B, VEC, kHintPlain>(a, st);
 }
 
 // Workgroups of a tile kernel that fit on one compute unit at once.

@@ -29,6 +29,8 @@ struct TileLaunch {
   uint32_t grid;            // workgroups (multiple of xcds)
   int pipelined;            // 1: persistent software-pipelined, 2: register-staged (in place)
   int hints = 0;            // CacheHint of the one-item 16-byte kernels
+  void* ev_start = nullptr; // hipEvent_t recorded as the kernel starts (or null)
+  void* ev_stop = nullptr;  // hipEvent_t recorded as it ends
 };
 
 struct WaveLaunch {

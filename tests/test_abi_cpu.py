@@ -119,6 +119,15 @@ def test_batched_validation(L):
     assert call(wsb=ws - 1) == br.ERROR_WORKSPACE
 
 
+def test_timed_entry_validation(L):
+    """The timed entry points need both events (checked before any HIP call)."""
+    assert L.bitrev_inplace_timed(FAKE, 20, 8, None, None, FAKE, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_inplace_timed(FAKE, 20, 8, None, FAKE, None, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_outofplace_timed(FAKE, FAKE + (8 << 20), 20, 8, None, None, None,
+                                     None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_inplace_timed(None, 20, 8, None, FAKE, FAKE, None) == br.ERROR_INVALID_VALUE
+
+
 def test_copy_validation(L):
     assert L.bitrev_copy_ex(FAKE, FAKE + 64, 16, 4, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_copy_ex(FAKE, FAKE + 64, 16, -1, None) == br.ERROR_INVALID_VALUE

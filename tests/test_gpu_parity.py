@@ -118,6 +118,26 @@ def test_cache_hints(s):
                                            "pad=%d" % (s, k, hints, inplace, variant, order, pad))
 
 
+def test_timed_entry():
+    """bitrev_inplace_timed permutes like bitrev_inplace, and the events its
+    kernel records bracket a positive time within the step's own events."""
+    for k, s in ((20, 8), (24, 8), (5, 4), (1, 8)):
+        host = workloads.byte_pattern((1 << k) * s, seed=k + 100)
+        x = to_device(host, s)
+        ka, kb, a, b = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        ka.record()
+        kb.record()
+        a.record()
+        br.bitrev_inplace_timed(x, ka, kb, k)
+        b.record()
+        torch.cuda.synchronize()
+        assert_bytes_equal(to_host_bytes(x), oracle.outofplace(host, s), "timed k=%d" % k)
+        kernel_ms, step_ms = ka.elapsed_time(kb), a.elapsed_time(b)
+        assert 0.0 <= kernel_ms <= step_ms + 1e-3, (k, kernel_ms, step_ms)
+    with pytest.raises(ValueError):
+        br.bitrev_inplace_timed(x, torch.cuda.Event(enable_timing=True), kb, 1)
+
+
 def test_copy_hints():
     """The reference copy with each cache hint copies every byte."""
     for nbytes in (1 << 20, (1 << 20) + 7):
