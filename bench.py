@@ -250,6 +250,56 @@ def other_configs(torch, br, timer, reps: int) -> dict:
     return out
 
 
+def traffic_workload(torch, br, workloads) -> None:
+    """A few calls of each main configuration, the caches evicted before
+    every call, for rocprofv3 counter runs: prints, per configuration in run
+    order, one JSON line with its library kernel dispatches per call and its
+    algorithmic bytes per call (2 n s per array)."""
+    timer = Timer(torch, flush=True)
+
+    def run(name, fn, calls, dispatches, nbytes):
+        for _ in range(calls):
+            timer._flush()
+            fn()
+        torch.cuda.synchronize()
+        print(json.dumps({"config": name, "calls": calls, "dispatches_per_call": dispatches,
+                          "algorithmic_bytes_per_call": int(nbytes)}), flush=True)
+
+    x = workloads.device_normal(1 << 24, workloads.SEEDS["c2"], torch.complex64)
+    y = torch.empty_like(x)
+    nb = 2 * x.numel() * 8
+    run("copy plain complex64 2^24 (calibration)", lambda: br.bitrev_copy(x, y, cache_hints=1),
+        3, 1, nb)
+    run("copy streaming loads complex64 2^24 (calibration)",
+        lambda: br.bitrev_copy(x, y, cache_hints=2), 3, 1, nb)
+    run("in place complex64 2^24", lambda: br.bitrev_inplace(x), 4, 1, nb)
+    run("out of place complex64 2^24", lambda: br.bitrev_outofplace(x, y), 3, 1, nb)
+    run("fused DIT 6 levels in place complex64 2^24", lambda: br.bitrev_dit_stages(x, x, 6), 3, 1, nb)
+    run("fused DIT 6 levels out of place complex64 2^24", lambda: br.bitrev_dit_stages(x, y, 6),
+        3, 1, nb)
+    run("radix-4 digit reversal in place complex64 2^24",
+        lambda: br.bitrev_digitrev_inplace(x, 2), 2, 1, nb)
+    del x, y
+    torch.cuda.empty_cache()
+    for name, k, dt, seed in (("complex128 2^28", 28, torch.complex128, workloads.SEEDS["c3a"]),
+                              ("float32 2^30", 30, torch.float32, workloads.SEEDS["c3b"])):
+        x = workloads.device_normal(1 << k, seed, dt)
+        y = torch.empty_like(x)
+        nb = 2 * x.numel() * x.element_size()
+        run("in place " + name, lambda: br.bitrev_inplace(x), 2, 1, nb)
+        run("out of place " + name, lambda: br.bitrev_outofplace(x, y), 2, 1, nb)
+        del x, y
+        torch.cuda.empty_cache()
+    offsets, log2n = workloads.batched_layout(4096, 8, 20, workloads.SEEDS["c4"])
+    data = workloads.device_normal(int(offsets[-1]), workloads.SEEDS["c4"] + 1000, torch.complex64)
+    off = torch.from_numpy(offsets).cuda()
+    l2 = torch.from_numpy(log2n).cuda()
+    ws = torch.empty(br.bitrev_batched_workspace_size(len(log2n)), dtype=torch.uint8,
+                     device="cuda")
+    run("batched 4096 complex64 arrays, log2n in [8, 20] (prep + main kernel)",
+        lambda: br.bitrev_batched(data, off, l2, ws), 2, 2, 2 * int(offsets[-1]) * 8)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +312,8 @@ def main() -> int:
     ap.add_argument("--tile-bits", type=int, default=0, help="force b (0: library plan)")
     ap.add_argument("--variant", type=int, default=0, help="force the tile kernel variant")
     ap.add_argument("--order", type=int, default=0, help="force the work-item order")
+    ap.add_argument("--traffic-workload", action="store_true",
+                    help="only run each main configuration a few times, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU form is a design "
@@ -280,6 +332,9 @@ def main() -> int:
         __graft_entry__.build()
     br.lib()
     torch.cuda.set_device(0)
+    if args.traffic_workload:
+        traffic_workload(torch, br, workloads)
+        return 0
     k, s = 24, 8
     n = 1 << k
     nbytes = 2.0 * n * s
