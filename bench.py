@@ -360,19 +360,17 @@ def main() -> int:
     # the kernel alone, for the roofline: the same steps under the same cache
     # flush, each launch recording HIP events from its own dispatch (that
     # launch path adds dispatch latency to the step, so it is not the step
-    # timed above)
-    kernel_events = []
-    for _ in range(args.steps):
-        ka = torch.cuda.Event(enable_timing=True)
-        kb = torch.cuda.Event(enable_timing=True)
-        ka.record()  # torch creates the HIP event on its first record
-        kb.record()
-        kernel_events.append((ka, kb))
+    # timed above).  The events skip the system-scope fence, whose L2
+    # writeback would otherwise land inside the stop timestamp.
+    kernel_events = [(br.TimingEvent(), br.TimingEvent()) for _ in range(args.steps)]
     for ka, kb in kernel_events:
         timer._flush()
         br.bitrev_inplace_timed(x, ka, kb, k, **cfg)
     torch.cuda.synchronize()
     kernel_ms = statistics.fmean(ka.elapsed_time(kb) for ka, kb in kernel_events)
+    for ev in kernel_events:
+        ev[0].destroy()
+        ev[1].destroy()
     applied_extra = args.steps
 
     # parity of the final state: an even number of applications is the input

@@ -223,13 +223,29 @@ bitrev_status_t bitrev_outofplace_ex(const void* src, void* dst, int log2n, size
  * enabled); both must be given (else BITREV_ERROR_INVALID_VALUE).  Where the
  * call runs no kernel the events are recorded back to back.  This launch path
  * adds dispatch latency on the stream (about 9 us measured on MI355X), so it
- * times the kernel, not the throughput of a sequence of calls. */
+ * times the kernel, not the throughput of a sequence of calls.  Events from
+ * bitrev_timing_event_create bracket the kernel alone; events created with
+ * default flags also include the writeback of the L2 that their system-scope
+ * fence performs (2-3 us after a 128 MiB in-place call on MI355X). */
 bitrev_status_t bitrev_inplace_timed(void* data, int log2n, size_t elem_size,
                                      const bitrev_config_t* cfg, void* start_event,
                                      void* stop_event, void* stream);
 bitrev_status_t bitrev_outofplace_timed(const void* src, void* dst, int log2n, size_t elem_size,
                                         const bitrev_config_t* cfg, void* start_event,
                                         void* stop_event, void* stream);
+/* Events for the *_timed entries.  bitrev_timing_event_create makes a HIP
+ * event with timing enabled and the system-scope fence disabled
+ * (hipEventDisableSystemFence): reaching it does not write back the L2, so
+ * it timestamps the kernel's end rather than the end of that writeback.  It
+ * is for timing only: it does not make the kernel's results visible to the
+ * host or to other devices.  The caller owns the event and frees it with
+ * bitrev_timing_event_destroy (NULL is a no-op).  bitrev_timing_elapsed_ms
+ * waits for stop_event and writes the milliseconds between the two events to
+ * *ms.  NULL arguments return BITREV_ERROR_INVALID_VALUE (create: event;
+ * elapsed: any); HIP failures return BITREV_ERROR_HIP. */
+bitrev_status_t bitrev_timing_event_create(void** event);
+bitrev_status_t bitrev_timing_event_destroy(void* event);
+bitrev_status_t bitrev_timing_elapsed_ms(void* start_event, void* stop_event, float* ms);
 bitrev_status_t bitrev_rows_ex(const void* src, void* dst, int log2n, int64_t rows,
                                size_t elem_size, const bitrev_config_t* cfg, void* stream);
 bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t* offsets,

@@ -80,6 +80,9 @@ _SIGNATURES = {
     "bitrev_outofplace_ex": ([_VP, _VP, _I, _SZ, _CFGP, _VP], _I),
     "bitrev_inplace_timed": ([_VP, _I, _SZ, _CFGP, _VP, _VP, _VP], _I),
     "bitrev_outofplace_timed": ([_VP, _VP, _I, _SZ, _CFGP, _VP, _VP, _VP], _I),
+    "bitrev_timing_event_create": ([ctypes.POINTER(_VP)], _I),
+    "bitrev_timing_event_destroy": ([_VP], _I),
+    "bitrev_timing_elapsed_ms": ([_VP, _VP, ctypes.POINTER(ctypes.c_float)], _I),
     "bitrev_rows_ex": ([_VP, _VP, _I, _I64, _SZ, _CFGP, _VP], _I),
     "bitrev_batched_ex": ([_VP, _I64, _VP, _VP, _I64, _SZ, _VP, _SZ, _CFGP, _VP], _I),
     "bitrev_plan_query": ([_I, _SZ, _I64, _I, _CFGP, ctypes.POINTER(Plan)], _I),
@@ -202,11 +205,37 @@ def bitrev_inplace(data, log2n: Optional[int] = None, *, tile_bits=0, grid_block
     return data
 
 
+class TimingEvent:
+    """A HIP timing event from bitrev_timing_event_create (system-scope fence
+    disabled, so that it timestamps the kernel's end and not the L2 writeback
+    such a fence adds): the start or stop event of the *_timed calls."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(_load().bitrev_timing_event_create(ctypes.byref(h)), "bitrev_timing_event_create")
+        self.handle = h.value
+
+    def elapsed_time(self, stop: "TimingEvent") -> float:
+        """Milliseconds from this event to ``stop`` (waits for ``stop``)."""
+        ms = ctypes.c_float()
+        _check(_load().bitrev_timing_elapsed_ms(ctypes.c_void_p(self.handle),
+                                                 ctypes.c_void_p(stop.handle), ctypes.byref(ms)),
+               "bitrev_timing_elapsed_ms")
+        return ms.value
+
+    def destroy(self) -> None:
+        if self.handle:
+            _check(_load().bitrev_timing_event_destroy(ctypes.c_void_p(self.handle)),
+                   "bitrev_timing_event_destroy")
+            self.handle = None
+
+
 def _event_handle(event, name):
-    handle = getattr(event, "cuda_event", 0)
+    handle = event.handle if isinstance(event, TimingEvent) else getattr(event, "cuda_event", 0)
     if not handle:
-        raise ValueError("%s must be a torch.cuda.Event(enable_timing=True) that has been "
-                         "recorded once (torch creates the HIP event on its first record)" % name)
+        raise ValueError("%s must be a TimingEvent, or a torch.cuda.Event(enable_timing=True) "
+                         "that has been recorded once (torch creates the HIP event on its "
+                         "first record)" % name)
     return ctypes.c_void_p(handle)
 
 
@@ -215,7 +244,8 @@ def bitrev_inplace_timed(data, start_event, stop_event, log2n: Optional[int] = N
                          cache_hints=0, config=None, stream=None):
     """bitrev_inplace whose kernel launch records ``start_event`` as the
     kernel starts and ``stop_event`` as it ends, so that
-    ``start_event.elapsed_time(stop_event)`` is the kernel's own duration."""
+    ``start_event.elapsed_time(stop_event)`` is the kernel's own duration
+    (TimingEvent: without the L2 writeback of a system-scope fence)."""
     ptr, s = _tensor_args(data, "data")
     k = _log2_exact(data.numel()) if log2n is None else int(log2n)
     cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
@@ -223,6 +253,24 @@ def bitrev_inplace_timed(data, start_event, stop_event, log2n: Optional[int] = N
                                         _event_handle(stop_event, "stop_event"), _stream(stream)),
            "bitrev_inplace_timed")
     return data
+
+
+def bitrev_outofplace_timed(src, dst, start_event, stop_event, log2n: Optional[int] = None, *,
+                            tile_bits=0, grid_blocks=0, order=0, variant=0, xcd_remap=0,
+                            cache_hints=0, config=None, stream=None):
+    """bitrev_outofplace with the kernel timed as in bitrev_inplace_timed."""
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2 or src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same element size and length")
+    k = _log2_exact(src.numel()) if log2n is None else int(log2n)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
+    _check(_load().bitrev_outofplace_timed(sp, dp, k, s, cfg,
+                                           _event_handle(start_event, "start_event"),
+                                           _event_handle(stop_event, "stop_event"),
+                                           _stream(stream)),
+           "bitrev_outofplace_timed")
+    return dst
 
 
 def bitrev_outofplace(src, dst=None, log2n: Optional[int] = None, *, tile_bits=0, grid_blocks=0,
@@ -493,7 +541,8 @@ def bitrev_tuning_format() -> str:
 
 
 __all__ = [
-    "BitrevError", "Config", "Plan", "lib", "abi_version", "status_string", "bitrev_inplace_timed",
+    "BitrevError", "Config", "Plan", "TimingEvent", "lib", "abi_version", "status_string",
+    "bitrev_inplace_timed", "bitrev_outofplace_timed",
     "bitrev_inplace", "bitrev_outofplace", "bitrev_rows", "bitrev_batched",
     "bitrev_batched_workspace_size", "bitrev_batched_errors", "bitrev_copy",
     "bitrev_plan_query", "bitrev_load_tuning", "bitrev_tuning_format",

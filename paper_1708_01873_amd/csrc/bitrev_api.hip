@@ -850,6 +850,31 @@ bitrev_status_t bitrev_outofplace_timed(const void* src, void* dst, int log2n, s
   return run_plain(src, dst, log2n, 1, elem_size, cfg, stream, 0, 0, start_event, stop_event);
 }
 
+bitrev_status_t bitrev_timing_event_create(void** event) {
+  if (event == NULL) return BITREV_ERROR_INVALID_VALUE;
+  *event = NULL;
+  hipEvent_t ev = NULL;
+  // no system-scope fence when the event is reached: the stop timestamp is
+  // then not delayed by the writeback of the L2 that such a fence performs
+  const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
+  if (e != hipSuccess) return hip_fail(e);
+  *event = (void*)ev;
+  return BITREV_SUCCESS;
+}
+
+bitrev_status_t bitrev_timing_event_destroy(void* event) {
+  if (event == NULL) return BITREV_SUCCESS;
+  const hipError_t e = hipEventDestroy((hipEvent_t)event);
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+bitrev_status_t bitrev_timing_elapsed_ms(void* start_event, void* stop_event, float* ms) {
+  if (start_event == NULL || stop_event == NULL || ms == NULL) return BITREV_ERROR_INVALID_VALUE;
+  hipError_t e = hipEventSynchronize((hipEvent_t)stop_event);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, (hipEvent_t)start_event, (hipEvent_t)stop_event);
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
 bitrev_status_t bitrev_outofplace(const void* src, void* dst, int log2n, size_t elem_size,
                                   void* stream) {
   if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;

@@ -445,6 +445,124 @@ __device__ __forceinline__ void tile_gather(Chunk<S, TileShape<S, B, VEC>::VB> (
   }
 }
 
+// ---------------------------------------------------------------------------
+// Swizzled LDS stage of the bit-reversal tile kernels for 8-byte elements
+// moved as 16-byte vectors.  An LDS row is 2^L 16-byte slots (L = b - 1) with
+// no padding, and logical slot c of row r is stored at slot c ^ swz(r),
+// swz(r) = rev_L(r mod 2^L).
+//
+// A thread holds chunk q and chunk q + CPT/2, i.e. source rows x and
+// x + R/2 at the same chunk index zc, whose destination columns rev_b(x) and
+// rev_b(x) + 1 are adjacent: each scatter write is one 16-byte slot, half the
+// LDS writes of the element-wise scatter.  The lanes of a wavefront hold
+// consecutive zc of one source row, bound for destination rows
+// r = rev_b(2 zc + j); the low L bits of such an r are rev_L(zc), so
+// swz(r) = zc and the lanes write distinct slots.  The row-order reads (2^L
+// lanes per row, XORed by one constant) are distinct slots too.  Neither
+// side has bank conflicts, where the padded layout's element-wise scatter lost
+// half its LDS cycles to them.  The tiles sit at the same offsets as in the
+// padded layout (a tile's pad is left unused).  16-byte elements keep the
+// padded layout: the same swizzle measured up to 2% slower for them.
+// ---------------------------------------------------------------------------
+template <int S, int B, bool VEC, int NT> constexpr bool lds_swizzled() {
+  typedef TileShape<S, B, VEC> Sh;
+  if (S != 8 || !VEC || Sh::VB != 16) return false;
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  return Sh::CPT % NT == 0 && PT % 2 == 0;
+}
+
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void tile_scatter_swz(const Chunk<S, 16> (&reg)[PT],
+                                                 typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<16>::T V;
+  constexpr int L = B - 1;
+  constexpr int HALF = PT / 2;
+  V* l = reinterpret_cast<V*>(lds);
+#pragma unroll
+  for (int i = 0; i < HALF; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    const uint32_t x = (uint32_t)(q / Sh::CPR);  // < R/2; chunk i + HALF is row x + R/2
+    const uint32_t zc = (uint32_t)(q % Sh::CPR);
+    const uint32_t slot = (rev_c<B>(x) >> 1) ^ zc;
+    // element j of both chunks, as whole-vector shuffles (a union copy here
+    // sends the register arrays to scratch memory)
+    const V a = reg[i].v, b = reg[i + HALF].v;
+    l[(rev_c<B>(2u * zc) << L) + slot] = __builtin_shufflevector(a, b, 0, 1, 4, 5);
+    l[(rev_c<B>(2u * zc + 1u) << L) + slot] = __builtin_shufflevector(a, b, 2, 3, 6, 7);
+  }
+}
+
+// Swizzled counterpart of tile_store.
+template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
+__device__ __forceinline__ void tile_store_swz(typename Bytes<S>::T* __restrict__ base,
+                                               uint64_t rowstride, uint32_t y,
+                                               const typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<16>::T V;
+  constexpr int L = B - 1;
+  const V* l = reinterpret_cast<const V*>(lds);
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    const uint32_t r = (uint32_t)(q / Sh::CPR);
+    const uint32_t cc = (uint32_t)(q % Sh::CPR);
+    const V v = l[(r << L) + (cc ^ rev_c<L>(r & ((1u << L) - 1u)))];
+    const uint64_t off = (uint64_t)r * rowstride + (uint64_t)y * Sh::R + (uint64_t)(cc * Sh::CE);
+    st_hint<H>(reinterpret_cast<V*>(base + off), v);
+  }
+}
+
+// Swizzled counterpart of tile_gather.
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void tile_gather_swz(Chunk<S, 16> (&reg)[PT],
+                                                const typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<16>::T V;
+  constexpr int L = B - 1;
+  const V* l = reinterpret_cast<const V*>(lds);
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int q = (int)threadIdx.x + i * NT;
+    const uint32_t r = (uint32_t)(q / Sh::CPR);
+    const uint32_t cc = (uint32_t)(q % Sh::CPR);
+    reg[i].v = l[(r << L) + (cc ^ rev_c<L>(r & ((1u << L) - 1u)))];
+  }
+}
+
+// The bit-reversal LDS stage: swizzled where lds_swizzled holds, padded
+// otherwise.  Scatter in destination order, then store or gather by rows.
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void rev_scatter(const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                            typename Bytes<S>::T* lds) {
+  if constexpr (lds_swizzled<S, B, VEC, NT>()) {
+    tile_scatter_swz<S, B, VEC, NT, PT>(reg, lds);
+  } else {
+    tile_scatter<S, B, VEC, NT, PT>(reg, lds);
+  }
+}
+
+template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
+__device__ __forceinline__ void rev_store(typename Bytes<S>::T* __restrict__ base,
+                                          uint64_t rowstride, uint32_t y,
+                                          const typename Bytes<S>::T* lds) {
+  if constexpr (lds_swizzled<S, B, VEC, NT>()) {
+    tile_store_swz<S, B, VEC, NT, PT, H>(base, rowstride, y, lds);
+  } else {
+    tile_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds);
+  }
+}
+
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void rev_gather(Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                           const typename Bytes<S>::T* lds) {
+  if constexpr (lds_swizzled<S, B, VEC, NT>()) {
+    tile_gather_swz<S, B, VEC, NT, PT>(reg, lds);
+  } else {
+    tile_gather<S, B, VEC, NT, PT>(reg, lds);
+  }
+}
+
 // Registers (as tile_gather left them) -> the rows of tile y in HBM.
 template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
 __device__ __forceinline__ void tile_put(const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
@@ -482,17 +600,73 @@ __device__ __forceinline__ void tile_pair_inplace_rs(typename Bytes<S>::T* __res
   Chunk<S, Sh::VB> ra[PT], rb[PT];
   tile_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
   if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
-  tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+  rev_scatter<S, B, VEC, NT, PT>(ra, lds);
   __syncthreads();
-  tile_gather<S, B, VEC, NT, PT>(ra, lds);  // tile y, transposed: its rows go to yr
+  rev_gather<S, B, VEC, NT, PT>(ra, lds);  // tile y, transposed: its rows go to yr
   if (!pal) {
     __syncthreads();
-    tile_scatter<S, B, VEC, NT, PT>(rb, lds);
+    rev_scatter<S, B, VEC, NT, PT>(rb, lds);
     __syncthreads();
-    tile_gather<S, B, VEC, NT, PT>(rb, lds);
+    rev_gather<S, B, VEC, NT, PT>(rb, lds);
     tile_put<S, B, VEC, NT, PT, H>(rb, base, rowstride, y);
   }
   tile_put<S, B, VEC, NT, PT, H>(ra, base, rowstride, yr);
+}
+
+// Element-wise tiles with more accesses per thread than registers can hold
+// (an array that is not 16-byte aligned, at a wide tile): elements go from
+// HBM straight into LDS in destination order and from LDS straight back, one
+// at a time, with no register staging.  In place, both tiles sit in LDS
+// before the barrier and are written after it.
+template <int S, int B, bool VEC, int NT> constexpr bool tile_elementwise() {
+  return !VEC && (TileShape<S, B, VEC>::CPT + NT - 1) / NT > 8;
+}
+
+template <int S, int B, int NT>
+__device__ __forceinline__ void tile_pair_inplace_elem(typename Bytes<S>::T* __restrict__ base,
+                                                       int m, uint32_t y,
+                                                       typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, false> Sh;
+  const uint64_t rowstride = 1ull << (m + B);
+  const uint32_t yr = rev_bits(y, m);
+  const bool pal = (yr == y);
+#pragma unroll 4
+  for (int q = (int)threadIdx.x; q < Sh::CPT; q += NT) {
+    const uint32_t x = (uint32_t)q >> B, z = (uint32_t)q & (Sh::R - 1);
+    const uint32_t d = rev_c<B>(z) * Sh::PE + rev_c<B>(x);
+    const uint64_t off = (uint64_t)x * rowstride + z;
+    lds[d] = base[off + (uint64_t)y * Sh::R];
+    if (!pal) lds[Sh::TILE_E + d] = base[off + (uint64_t)yr * Sh::R];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int q = (int)threadIdx.x; q < Sh::CPT; q += NT) {
+    const uint32_t r = (uint32_t)q >> B, c = (uint32_t)q & (Sh::R - 1);
+    const uint64_t off = (uint64_t)r * rowstride + c;
+    if (!pal) base[off + (uint64_t)y * Sh::R] = lds[Sh::TILE_E + r * Sh::PE + c];
+    base[off + (uint64_t)yr * Sh::R] = lds[r * Sh::PE + c];
+  }
+}
+
+template <int S, int B, int NT>
+__device__ __forceinline__ void tile_outofplace_elem(const typename Bytes<S>::T* __restrict__ src,
+                                                     typename Bytes<S>::T* __restrict__ dst,
+                                                     int m, uint32_t y,
+                                                     typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, false> Sh;
+  const uint64_t rowstride = 1ull << (m + B);
+  const uint32_t yr = rev_bits(y, m);
+#pragma unroll 4
+  for (int q = (int)threadIdx.x; q < Sh::CPT; q += NT) {
+    const uint32_t x = (uint32_t)q >> B, z = (uint32_t)q & (Sh::R - 1);
+    lds[rev_c<B>(z) * Sh::PE + rev_c<B>(x)] = src[(uint64_t)x * rowstride + (uint64_t)y * Sh::R + z];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int q = (int)threadIdx.x; q < Sh::CPT; q += NT) {
+    const uint32_t r = (uint32_t)q >> B, c = (uint32_t)q & (Sh::R - 1);
+    dst[(uint64_t)r * rowstride + (uint64_t)yr * Sh::R + c] = lds[r * Sh::PE + c];
+  }
 }
 
 // In place: swap tiles y and yr = rev_m(y) of the array at `base` (one tile
@@ -501,6 +675,10 @@ __device__ __forceinline__ void tile_pair_inplace_rs(typename Bytes<S>::T* __res
 template <int S, int B, bool VEC, int NT, int H = kHintPlain>
 __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restrict__ base, int m,
                                                   uint32_t y, typename Bytes<S>::T* lds) {
+  if constexpr (tile_elementwise<S, B, VEC, NT>()) {
+    tile_pair_inplace_elem<S, B, NT>(base, m, y, lds);
+    return;
+  }
   typedef TileShape<S, B, VEC> Sh;
   constexpr int PT = (Sh::CPT + NT - 1) / NT;
   const uint64_t rowstride = 1ull << (m + B);
@@ -509,13 +687,13 @@ __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restri
   Chunk<S, Sh::VB> ra[PT], rb[PT];
   tile_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
   if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
-  tile_scatter<S, B, VEC, NT, PT>(ra, lds);
-  if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+  rev_scatter<S, B, VEC, NT, PT>(ra, lds);
+  if (!pal) rev_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
   __syncthreads();
   // tile y first, then its partner: measured a few percent faster than the
   // other order for arrays that fit the Infinity Cache
-  if (!pal) tile_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds + Sh::TILE_E);
-  tile_store<S, B, VEC, NT, PT, H>(base, rowstride, yr, lds);
+  if (!pal) rev_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds + Sh::TILE_E);
+  rev_store<S, B, VEC, NT, PT, H>(base, rowstride, yr, lds);
 }
 
 // Out of place: tile y of `src` to tile rev_m(y) of `dst`.
@@ -523,14 +701,18 @@ template <int S, int B, bool VEC, int NT, int H = kHintPlain>
 __device__ __forceinline__ void tile_outofplace(const typename Bytes<S>::T* __restrict__ src,
                                                 typename Bytes<S>::T* __restrict__ dst, int m,
                                                 uint32_t y, typename Bytes<S>::T* lds) {
+  if constexpr (tile_elementwise<S, B, VEC, NT>()) {
+    tile_outofplace_elem<S, B, NT>(src, dst, m, y, lds);
+    return;
+  }
   typedef TileShape<S, B, VEC> Sh;
   constexpr int PT = (Sh::CPT + NT - 1) / NT;
   const uint64_t rowstride = 1ull << (m + B);
   Chunk<S, Sh::VB> ra[PT];
   tile_load<S, B, VEC, NT, PT, H>(ra, src, rowstride, y);
-  tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+  rev_scatter<S, B, VEC, NT, PT>(ra, lds);
   __syncthreads();
-  tile_store<S, B, VEC, NT, PT, H>(dst, rowstride, rev_bits(y, m), lds);
+  rev_store<S, B, VEC, NT, PT, H>(dst, rowstride, rev_bits(y, m), lds);
 }
 
 // ---------------------------------------------------------------------------

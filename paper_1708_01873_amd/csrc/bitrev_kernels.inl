@@ -124,8 +124,8 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace_pi
   tile_load<S, B, VEC, NT, PT>(ra, base, rowstride, y);
   if (yr != y) tile_load<S, B, VEC, NT, PT>(rb, base, rowstride, yr);
   while (true) {
-    tile_scatter<S, B, VEC, NT, PT>(ra, lds);
-    if (yr != y) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+    rev_scatter<S, B, VEC, NT, PT>(ra, lds);
+    if (yr != y) rev_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
     __syncthreads();
     const uint64_t next = item + gridDim.x;
     E* nbase = base;
@@ -137,8 +137,8 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_inplace_pi
       tile_load<S, B, VEC, NT, PT>(ra, nbase, rowstride, ny);
       if (nyr != ny) tile_load<S, B, VEC, NT, PT>(rb, nbase, rowstride, nyr);
     }
-    if (yr != y) tile_store<S, B, VEC, NT, PT>(base, rowstride, y, lds + Sh::TILE_E);
-    tile_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
+    if (yr != y) rev_store<S, B, VEC, NT, PT>(base, rowstride, y, lds + Sh::TILE_E);
+    rev_store<S, B, VEC, NT, PT>(base, rowstride, yr, lds);
     if (next >= total_items) break;
     __syncthreads();
     item = next;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
   uint32_t y = oop_tile_at(m, (uint32_t)local, balanced);
   tile_load<S, B, VEC, NT, PT>(ra, in, rowstride, y);
   while (true) {
-    tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+    rev_scatter<S, B, VEC, NT, PT>(ra, lds);
     __syncthreads();
     const uint64_t next = item + gridDim.x;
     const E* nin = in;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
       ny = oop_tile_at(m, (uint32_t)local, balanced);
       tile_load<S, B, VEC, NT, PT>(ra, nin, rowstride, ny);
     }
-    tile_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
+    rev_store<S, B, VEC, NT, PT>(out, rowstride, rev_bits(y, m), lds);
     if (next >= total_items) break;
     __syncthreads();
     item = next;

@@ -126,6 +126,13 @@ def test_timed_entry_validation(L):
     assert L.bitrev_outofplace_timed(FAKE, FAKE + (8 << 20), 20, 8, None, None, None,
                                      None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_inplace_timed(None, 20, 8, None, FAKE, FAKE, None) == br.ERROR_INVALID_VALUE
+    # timing events: NULL arguments are refused before any HIP call
+    ms = ctypes.c_float()
+    assert L.bitrev_timing_event_create(None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_timing_event_destroy(None) == br.SUCCESS
+    assert L.bitrev_timing_elapsed_ms(None, FAKE, ctypes.byref(ms)) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_timing_elapsed_ms(FAKE, None, ctypes.byref(ms)) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_timing_elapsed_ms(FAKE, FAKE, None) == br.ERROR_INVALID_VALUE
 
 
 def test_copy_validation(L):
@@ -393,3 +400,32 @@ def test_variant_entry_validation(L):
     assert L.bitrev_batched_outofplace(FAKE, FAKE + 64, 1024, FAKE, FAKE, 4, 8, FAKE, ws, None) == br.ERROR_ALIAS
     assert L.bitrev_batched_outofplace(None, FAKE, 1024, FAKE, FAKE, 4, 8, FAKE, ws, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_batched_outofplace(FAKE, FAKE + (1 << 20), 1024, FAKE, FAKE, 4, 8, FAKE, 8, None) == br.ERROR_WORKSPACE
+
+
+def test_kernel_resource_remarks():
+    """The build reads hipcc's per-kernel resource remarks and refuses any
+    kernel that spills to scratch memory; the recorded figures of the last
+    build keep every kernel in registers and LDS."""
+    from paper_1708_01873_amd import build as bld
+    text = "\n".join([
+        "x.inl:1:1: remark: Function Name: kern_a [-Rpass-analysis=kernel-resource-usage]",
+        "x.inl:1:1: remark:     VGPRs: 46 [-Rpass-analysis=kernel-resource-usage]",
+        "x.inl:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.inl:1:1: remark:     Occupancy [waves/SIMD]: 8 [-Rpass-analysis=kernel-resource-usage]",
+        "x.inl:1:1: remark:     LDS Size [bytes/block]: 66560 [-Rpass-analysis=kernel-resource-usage]",
+        "x.inl:2:1: remark: Function Name: kern_b [-Rpass-analysis=kernel-resource-usage]",
+        "x.inl:2:1: remark:     ScratchSize [bytes/lane]: 16 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    ks = bld.parse_resources(text)
+    assert ks == [{"name": "kern_a", "VGPRs": 46, "ScratchSize": 0, "Occupancy": 8,
+                   "LDS Size": 66560},
+                  {"name": "kern_b", "ScratchSize": 16}]
+    if not os.path.exists(bld.RESOURCES):
+        pytest.skip("no build record")
+    rows = [ln.split() for ln in open(bld.RESOURCES) if not ln.startswith("#")]
+    assert len(rows) > 100
+    assert all(r[3] == "0" for r in rows), [r[0] for r in rows if r[3] != "0"]
+    # the in-place complex64 tile kernel at b = 6: two 1024-thread
+    # workgroups per CU need at most 64 VGPRs
+    head = [r for r in rows if "k_tile_inplaceILi8ELi6ELb1E" in r[0]]
+    assert head and all(int(r[1]) <= 64 for r in head)

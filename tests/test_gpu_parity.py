@@ -97,6 +97,21 @@ def test_element_aligned_base(s):
             assert_bytes_equal(got, want, "misaligned s=%d k=%d ip=%s" % (s, k, inplace))
 
 
+@pytest.mark.parametrize("s", (1, 2, 4))
+def test_element_aligned_wide_tiles(s):
+    """Element-aligned bases at the widest tile, where the per-element path
+    moves elements between HBM and LDS one at a time (no register staging):
+    palindromic and swapped tiles, odd and even middle widths."""
+    for k in (14, 15, 17):
+        host = workloads.byte_pattern((1 << k) * s, seed=100 + k)
+        want = oracle.outofplace(host, s)
+        for variant in (1, 2):
+            for inplace in (True, False):
+                got = _run(host, k, s, inplace, pad_front=1, tile_bits=7, variant=variant)
+                assert_bytes_equal(got, want, "misaligned b=7 s=%d k=%d variant=%d ip=%s"
+                                   % (s, k, variant, inplace))
+
+
 @pytest.mark.parametrize("s", ELEM_SIZES)
 def test_cache_hints(s):
     """Every cache-hint instance of the one-item tile kernels and of the
@@ -136,6 +151,35 @@ def test_timed_entry():
         assert 0.0 <= kernel_ms <= step_ms + 1e-3, (k, kernel_ms, step_ms)
     with pytest.raises(ValueError):
         br.bitrev_inplace_timed(x, torch.cuda.Event(enable_timing=True), kb, 1)
+
+
+def test_timing_events():
+    """The library's fence-free timing events with both timed entries: the
+    results match the oracle, and the kernel's time is positive and within
+    the step's own events."""
+    for k, s in ((24, 8), (16, 4), (3, 16)):
+        host = workloads.byte_pattern((1 << k) * s, seed=k + 200)
+        want = oracle.outofplace(host, s)
+        ka, kb = br.TimingEvent(), br.TimingEvent()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        x = to_device(host, s)
+        a.record()
+        br.bitrev_inplace_timed(x, ka, kb, k)
+        b.record()
+        torch.cuda.synchronize()
+        assert_bytes_equal(to_host_bytes(x), want, "timed events ip k=%d" % k)
+        kernel_ms, step_ms = ka.elapsed_time(kb), a.elapsed_time(b)
+        assert 0.0 <= kernel_ms <= step_ms + 1e-3, (k, kernel_ms, step_ms)
+        if k == 24:
+            assert kernel_ms > 0.0
+        x = to_device(host, s)
+        y = to_device(np.zeros_like(host), s)
+        br.bitrev_outofplace_timed(x, y, ka, kb, k)
+        assert ka.elapsed_time(kb) >= 0.0
+        assert_bytes_equal(to_host_bytes(y), want, "timed events oop k=%d" % k)
+        ka.destroy()
+        kb.destroy()
+        ka.destroy()  # a second destroy is a no-op
 
 
 def test_copy_hints():
