@@ -750,16 +750,39 @@ __device__ __forceinline__ void make_twiddles(typename ComplexOf<S>::T* tw) {
   }
 }
 
-// Levels 1 .. stages of the radix-2 DIT butterflies on `rows` staged rows:
-// for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b), w = exp(-+ 2 pi i / 2^s)
-// (sign + for the inverse).  Two levels s, s+1 run in one pass over LDS as a
-// radix-4 step on the four elements t, t+h, t+2h, t+3h (h = 2^(s-1)) of a
-// block: the same butterflies, where level s+1's second twiddle
-// w_{s+1}^(t+h) = w_{s+1}^t * (-+ i) is applied exactly.  A barrier ends each
-// pass; the caller then writes the rows with tile_store (measured faster
-// than storing the last pass's results directly: 16-byte row stores
-// coalesce better than the butterflies' 8-byte element stores).
-template <int S, int B, int NT>
+// Levels 1 .. stages of the radix-2 DIT butterflies on `rows` staged rows
+// (2^b or 2^(b+1)): for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b),
+// w = exp(-+ 2 pi i / 2^s) (sign + for the inverse).  Up to three levels run
+// in one pass over LDS: levels s, s+1, s+2 as a radix-8 step on the eight
+// elements t + j h (j < 8, h = 2^(s-1)) of a block of 2^(s+2), then a radix-4
+// step (levels s, s+1 on t + j h, j < 4) and a radix-2 tail, so that L levels
+// take ceil(L / 3) passes or one more.  Each step applies the same radix-2
+// butterflies as level-by-level code; the twiddles come from the table, and
+// a twiddle w_n^(p + n/4) = w_n^p * (-+ i) is applied exactly as that
+// rotation.  A barrier ends each pass.  Lanes take consecutive rows at one
+// butterfly position: with the padded row pitch their addresses are one
+// element apart modulo the banks, free of conflicts at every level, and they
+// read the same twiddle.  MAXR = 4 leaves out the radix-8 step (it holds
+// eight complex values per thread).  The caller then writes the rows with tile_store
+// (measured faster than storing the last pass's results directly: 16-byte
+// row stores coalesce better than the butterflies' 8-byte element stores).
+template <typename F>
+__device__ __forceinline__ void bfly(F& ar, F& ai, F& br, F& bi, F wr, F wi) {
+  const F tr = br * wr - bi * wi, ti = br * wi + bi * wr;
+  br = ar - tr;
+  bi = ai - ti;
+  ar = ar + tr;
+  ai = ai + ti;
+}
+
+// (r, i) * (-+ i): (i, -r) forward, (-i, r) inverse, exactly.
+template <typename F>
+__device__ __forceinline__ void rot_quarter(F wr, F wi, F sg, F* rr, F* ri) {
+  *rr = sg * wi;
+  *ri = -sg * wr;
+}
+
+template <int S, int B, int NT, int MAXR = 8>
 __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, int stages,
                                          bool inverse, const typename ComplexOf<S>::T* tw) {
   typedef typename ComplexOf<S>::T F;
@@ -767,54 +790,86 @@ __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, in
   constexpr int PE = TileShape<S, B, true>::PE;
   F* base = reinterpret_cast<F*>(lds);
   const F sg = inverse ? (F)-1 : (F)1;  // conjugates the forward twiddles
+  const int rsh = rows > R ? B + 1 : B;  // rows is 2^b or 2^(b+1)
   int s = 1;
   while (s <= stages) {
     const int h = 1 << (s - 1);
-    if (s + 1 <= stages) {
+    if (MAXR >= 8 && s + 2 <= stages) {
+      for (int beta = (int)threadIdx.x; beta < rows * (R / 8); beta += NT) {
+        const int row = beta & (rows - 1);
+        const int tp = beta >> rsh;
+        const int t = tp & (h - 1);
+        F* p = base + 2 * (row * PE + ((tp >> (s - 1)) << (s + 2)) + t);
+        F xr[8], xi[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          xr[j] = p[2 * j * h];
+          xi[j] = p[2 * j * h + 1];
+        }
+        // level s: pairs (j, j+1), twiddle w_{2h}^t
+        const F w1r = tw[2 * t * (R >> s)], w1i = sg * tw[2 * t * (R >> s) + 1];
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) bfly(xr[j], xi[j], xr[j + 1], xi[j + 1], w1r, w1i);
+        // level s+1: pairs (j, j+2), w_{4h}^t and w_{4h}^(t+h) = w_{4h}^t (-+ i)
+        const F w2r = tw[2 * t * (R >> (s + 1))], w2i = sg * tw[2 * t * (R >> (s + 1)) + 1];
+        F w2qr, w2qi;
+        rot_quarter(w2r, w2i, sg, &w2qr, &w2qi);
+        bfly(xr[0], xi[0], xr[2], xi[2], w2r, w2i);
+        bfly(xr[4], xi[4], xr[6], xi[6], w2r, w2i);
+        bfly(xr[1], xi[1], xr[3], xi[3], w2qr, w2qi);
+        bfly(xr[5], xi[5], xr[7], xi[7], w2qr, w2qi);
+        // level s+2: pairs (j, j+4), w_{8h}^(t+jh); j = 2, 3 are j = 0, 1
+        // rotated by (-+ i)
+        const int i3 = 2 * t * (R >> (s + 2)), i3h = 2 * (t + h) * (R >> (s + 2));
+        const F w3r = tw[i3], w3i = sg * tw[i3 + 1];
+        const F w4r = tw[i3h], w4i = sg * tw[i3h + 1];
+        F w3qr, w3qi, w4qr, w4qi;
+        rot_quarter(w3r, w3i, sg, &w3qr, &w3qi);
+        rot_quarter(w4r, w4i, sg, &w4qr, &w4qi);
+        bfly(xr[0], xi[0], xr[4], xi[4], w3r, w3i);
+        bfly(xr[1], xi[1], xr[5], xi[5], w4r, w4i);
+        bfly(xr[2], xi[2], xr[6], xi[6], w3qr, w3qi);
+        bfly(xr[3], xi[3], xr[7], xi[7], w4qr, w4qi);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) store_cplx(p + 2 * j * h, xr[j], xi[j]);
+      }
+      s += 3;
+    } else if (s + 1 <= stages) {
       const int q4 = R >= 4 ? R / 4 : 1;  // R = 2 never gets here (stages <= b)
       for (int beta = (int)threadIdx.x; beta < rows * q4; beta += NT) {
-        const int row = beta / q4;
-        const int tp = beta % q4;
+        const int row = beta & (rows - 1);
+        const int tp = beta >> rsh;
         const int t = tp & (h - 1);
-        const int c0 = ((tp >> (s - 1)) << (s + 1)) + t;
-        F* p0 = base + 2 * (row * PE + c0);
-        F* p1 = p0 + 2 * h;
-        F* p2 = p0 + 4 * h;
-        F* p3 = p0 + 6 * h;
+        F* p = base + 2 * (row * PE + ((tp >> (s - 1)) << (s + 1)) + t);
+        F xr[4], xi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          xr[j] = p[2 * j * h];
+          xi[j] = p[2 * j * h + 1];
+        }
         const F w1r = tw[2 * t * (R >> s)], w1i = sg * tw[2 * t * (R >> s) + 1];
+        bfly(xr[0], xi[0], xr[1], xi[1], w1r, w1i);
+        bfly(xr[2], xi[2], xr[3], xi[3], w1r, w1i);
         const F w2r = tw[2 * t * (R >> (s + 1))], w2i = sg * tw[2 * t * (R >> (s + 1)) + 1];
-        const F a0r = p0[0], a0i = p0[1], a1r = p1[0], a1i = p1[1];
-        const F a2r = p2[0], a2i = p2[1], a3r = p3[0], a3i = p3[1];
-        // level s: (a0, a1) and (a2, a3) with w1
-        const F t1r = a1r * w1r - a1i * w1i, t1i = a1r * w1i + a1i * w1r;
-        const F t3r = a3r * w1r - a3i * w1i, t3i = a3r * w1i + a3i * w1r;
-        const F x0r = a0r + t1r, x0i = a0i + t1i, x1r = a0r - t1r, x1i = a0i - t1i;
-        const F x2r = a2r + t3r, x2i = a2i + t3i, x3r = a2r - t3r, x3i = a2i - t3i;
-        // level s+1: (x0, x2) with w2, (x1, x3) with w2 * (-+ i)
-        const F u2r = x2r * w2r - x2i * w2i, u2i = x2r * w2i + x2i * w2r;
-        const F v3r = x3r * w2r - x3i * w2i, v3i = x3r * w2i + x3i * w2r;
-        const F u3r = sg * v3i, u3i = -sg * v3r;  // v3 * (-i), or * (+i) inverse
-        store_cplx(p0, x0r + u2r, x0i + u2i);
-        store_cplx(p2, x0r - u2r, x0i - u2i);
-        store_cplx(p1, x1r + u3r, x1i + u3i);
-        store_cplx(p3, x1r - u3r, x1i - u3i);
+        F w2qr, w2qi;
+        rot_quarter(w2r, w2i, sg, &w2qr, &w2qi);
+        bfly(xr[0], xi[0], xr[2], xi[2], w2r, w2i);
+        bfly(xr[1], xi[1], xr[3], xi[3], w2qr, w2qi);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) store_cplx(p + 2 * j * h, xr[j], xi[j]);
       }
       s += 2;
     } else {
-      const int H = R / 2;
-      for (int beta = (int)threadIdx.x; beta < rows * H; beta += NT) {
-        const int row = beta / H;
-        const int tp = beta % H;
+      for (int beta = (int)threadIdx.x; beta < rows * (R / 2); beta += NT) {
+        const int row = beta & (rows - 1);
+        const int tp = beta >> rsh;
         const int t = tp & (h - 1);
-        const int c0 = ((tp >> (s - 1)) << s) + t;
-        F* pa = base + 2 * (row * PE + c0);
+        F* pa = base + 2 * (row * PE + ((tp >> (s - 1)) << s) + t);
         F* pb = pa + 2 * h;
-        const F wr = tw[2 * t * (R >> s)], wi = sg * tw[2 * t * (R >> s) + 1];
-        const F ar = pa[0], ai = pa[1], br = pb[0], bi = pb[1];
-        const F tr = br * wr - bi * wi;
-        const F ti = br * wi + bi * wr;
-        store_cplx(pa, ar + tr, ai + ti);
-        store_cplx(pb, ar - tr, ai - ti);
+        F ar = pa[0], ai = pa[1], br = pb[0], bi = pb[1];
+        bfly(ar, ai, br, bi, tw[2 * t * (R >> s)], sg * tw[2 * t * (R >> s) + 1]);
+        store_cplx(pa, ar, ai);
+        store_cplx(pb, br, bi);
       }
       s += 1;
     }

@@ -206,9 +206,14 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_transpose_inpla
 
 #if BITREV_S == 8 || BITREV_S == 16
 // Bit reversal fused with the first `stages` radix-2 DIT levels (complex
-// elements), out of place (src != dst) or in place (src == dst, tile pairs).
-// Bit reversal fused with the first `stages` radix-2 DIT levels (complex
-// elements), in place (tile pairs) or out of place.
+// elements), in place (tile pairs) or out of place.  The radix-8 step of
+// dit_rows is used for complex64 except in place at b = 6, where it needs
+// more than the 64 VGPRs that two 1024-thread workgroups per CU allow (it
+// measured 15% slower there at six levels); complex128 (double registers)
+// lost occupancy and 2-10% with it at every width, and keeps radix 4.
+template <int S, int B, bool INPLACE>
+constexpr int dit_max_radix() { return (S == 8 && !(INPLACE && B >= 6)) ? 8 : 4; }
+
 template <int S, int B, bool VEC, bool INPLACE, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
@@ -241,7 +246,8 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
       __syncthreads();
-      dit_rows<S, B, NT>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw);
+      dit_rows<S, B, NT, dit_max_radix<S, B, true>()>(lds, pal ? Sh::R : 2 * Sh::R, stages,
+                                                        inverse != 0, tw);
       if (!pal) tile_store<S, B, VEC, NT, PT, H>(out, rowstride, y, lds + Sh::TILE_E);
       tile_store<S, B, VEC, NT, PT, H>(out, rowstride, yr, lds);
     } else {
@@ -249,7 +255,7 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
       tile_load<S, B, VEC, NT, PT, H>(ra, in, rowstride, y);
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       __syncthreads();
-      dit_rows<S, B, NT>(lds, Sh::R, stages, inverse != 0, tw);
+      dit_rows<S, B, NT, dit_max_radix<S, B, false>()>(lds, Sh::R, stages, inverse != 0, tw);
       tile_store<S, B, VEC, NT, PT, H>(out, rowstride, rev_bits(y, m), lds);
     }
     __syncthreads();
