@@ -87,11 +87,16 @@ typedef struct bitrev_config {
                     * robin), 2 = leave the dispatch order as is */
   int cache_hints; /* tile kernels' global accesses: 0 = choose, 1 = plain,
                     * 2 = streaming (non-temporal) loads, 3 = streaming
-                    * stores; applies to the one-item and register-staged
+                    * stores, 4 = streaming loads and write-through stores
+                    * (device scope: each written line goes through the
+                    * XCD's L2 to the memory side instead of staying dirty
+                    * there); applies to the one-item and register-staged
                     * tile kernels with 16-byte accesses, otherwise plain.
-                    * The choice: streaming loads beyond 32 MiB out of place
-                    * and beyond 64 MiB in place, except 8-byte elements in
-                    * place up to 256 MiB, which take streaming stores */
+                    * The choice: plain below 32 MiB out of place and 64 MiB
+                    * in place; streaming stores for 8-byte elements in
+                    * place above 64 MiB up to 128 MiB; streaming loads for
+                    * 1- and 2-byte elements beyond 256 MiB and for 4-byte
+                    * elements out of place at 128-256 MiB; 4 otherwise */
 } bitrev_config_t;
 
 /* Which code path and geometry a call uses (bitrev_plan_query). */
@@ -112,7 +117,8 @@ typedef struct bitrev_plan {
   int vector_access;    /* 1: 16-byte global accesses; 0: one element per access */
   int variant;          /* 1 one item per workgroup, 2 persistent pipelined, 3 register-staged */
   int xcd_remap;        /* 1 contiguous ranges per XCD, 2 dispatch order */
-  int cache_hints;      /* 1 plain, 2 streaming loads, 3 streaming stores */
+  int cache_hints;      /* 1 plain, 2 streaming loads, 3 streaming stores,
+                         * 4 streaming loads and write-through stores */
   uint64_t work_items;  /* tile pairs (in place) or tiles (out of place), all rows */
   uint64_t lds_bytes;   /* LDS per workgroup */
 } bitrev_plan_t;
@@ -343,9 +349,9 @@ bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_s
 /* dst[0 .. bytes) = src[0 .. bytes): a plain streaming copy with the same
  * byte count as an out-of-place permutation, used to measure attainable HBM
  * bandwidth.  Ranges must not overlap.  bitrev_copy takes the cache hint
- * measured fastest for the size (streaming loads above 256 MiB, where the
- * copy no longer fits the Infinity Cache); bitrev_copy_ex takes it from
- * cache_hints as in bitrev_config_t (0 = that choice). */
+ * measured fastest (streaming loads and write-through stores, at 128 MiB and
+ * at 4 GiB); bitrev_copy_ex takes it from cache_hints as in bitrev_config_t
+ * (0 = that choice). */
 bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream);
 bitrev_status_t bitrev_copy_ex(const void* src, void* dst, size_t bytes, int cache_hints,
                                void* stream);

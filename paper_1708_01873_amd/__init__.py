@@ -32,6 +32,7 @@ ORDER_DEFAULT, ORDER_NATURAL, ORDER_BALANCED, ORDER_GROUPED = 0, 1, 2, 3
 VARIANT_DEFAULT, VARIANT_ONE_ITEM, VARIANT_PIPELINED, VARIANT_REGISTER_STAGED = 0, 1, 2, 3
 XCD_DEFAULT, XCD_REMAP, XCD_DISPATCH_ORDER = 0, 1, 2
 HINTS_DEFAULT, HINTS_PLAIN, HINTS_STREAM_LOADS, HINTS_STREAM_STORES = 0, 1, 2, 3
+HINTS_STREAM_WRITE_THROUGH = 4  # streaming loads, write-through (device-scope) stores
 
 
 class BitrevError(RuntimeError):

@@ -100,7 +100,8 @@ const char kTuningFormat[] =
     "wg_per_cu(0 = default) order(0 = default, 1 natural, 2 balanced, 3 grouped) "
     "variant(0 = default, 1 one item per workgroup, 2 persistent pipelined, 3 register-staged) "
     "xcd_remap(0 = default, 1 contiguous ranges per XCD, 2 dispatch order) "
-    "[cache_hints(0 = default, 1 plain, 2 streaming loads, 3 streaming stores)]";
+    "[cache_hints(0 = default, 1 plain, 2 streaming loads, 3 streaming stores, "
+    "4 streaming loads and write-through stores)]";
 
 int mode_from_name(const char* s) {
   if (strcmp(s, "inplace") == 0) return 0;
@@ -134,7 +135,7 @@ bitrev_status_t load_tuning_file(const char* path) {
     const int md = got >= 8 ? mode_from_name(mode) : -1;
     if ((got != 8 && got != 9) || md < 0 || !valid_elem_size((size_t)s) || k < -1 ||
         k > BITREV_MAX_LOG2N || b < 0 || b > kMaxTileBits || wg < 0 || wg > 1024 || order < 0 ||
-        order > 3 || variant < 0 || variant > 3 || xcd < 0 || xcd > 2 || hints < 0 || hints > 3) {
+        order > 3 || variant < 0 || variant > 3 || xcd < 0 || xcd > 2 || hints < 0 || hints > 4) {
       ok = false;
       break;
     }
@@ -187,6 +188,7 @@ struct DefaultPlan {
   int variant;   // 1 one item per workgroup, 2 persistent pipelined, 3 register-staged
   int order;     // 1 natural, 2 balanced, 3 grouped
   int xcd_remap; // 1 contiguous ranges per XCD, 2 dispatch order
+  int wg_per_cu = 0;  // batched: persistent workgroups per CU (0 = as many as fit)
 };
 
 DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
@@ -217,7 +219,9 @@ DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
   }
   if (mode == 2) {  // batched (in place, persistent): complex64 measured on 4096 uneven arrays
     switch (s) {
-      case 8: return {6, 0, 1, 1};
+      // complex64: one 1024-thread workgroup per CU; two fit (62 VGPRs,
+      // 65 KiB of LDS each) but measured 4.5% slower on the 4096-array batch
+      case 8: return {6, 0, 1, 1, 1};
       case 16: return {5, 0, 2, 1};
       default: return {default_plan(0, s, 0).b, 0, 2, 1};
     }
@@ -280,7 +284,7 @@ bool valid_config(const bitrev_config_t* c) {
   if (!c) return true;
   return c->tile_bits >= 0 && c->tile_bits <= kMaxTileBits && c->grid_blocks >= 0 &&
          c->order >= 0 && c->order <= 3 && c->variant >= 0 && c->variant <= 3 &&
-         c->xcd_remap >= 0 && c->xcd_remap <= 2 && c->cache_hints >= 0 && c->cache_hints <= 3;
+         c->xcd_remap >= 0 && c->xcd_remap <= 2 && c->cache_hints >= 0 && c->cache_hints <= 4;
 }
 
 uint32_t round_up(uint64_t v, uint32_t to) {
@@ -300,17 +304,25 @@ int resident_per_cu(int threads, size_t lds);
 // The Infinity Cache of MI355X: arrays beyond it stream through HBM.
 constexpr uint64_t kCacheBytes = 256ull << 20;
 
-// Cache hints of the built-in plans, from a sweep over element sizes and
-// array sizes: out of place, streaming loads never cost and gain most beyond
-// the Infinity Cache (complex64 2^26: +15%, float32 2^28: +10%); in place,
-// streaming loads gain beyond it (+2-5%) while complex64 arrays within it do
-// better with streaming stores (64 MiB: +7%; loads cost 3% at 128 MiB).
+// Cache hints of the built-in plans, from sweeps over element sizes (1-16
+// bytes) and array sizes (64 MiB - 4 GiB) on random data.  Streaming loads
+// with write-through stores were the best or tied form almost everywhere:
+// complex64 in place +4.5% at 64 MiB and +7.7% at 256 MiB over streaming
+// stores; out of place +3-6%; complex128 and float32 +1-5%.  Complex64 in
+// place of 64-128 MiB keeps streaming stores (at 128 MiB 0.5% faster per
+// call and 1% per kernel, ten alternating rounds).  Streaming loads alone
+// stay where they measured ahead: 1- and 2-byte elements beyond the Infinity
+// Cache (out of place +15%) and float32 out of place at 256 MiB (+4%).
+// Below 32 MiB (out of place) or 64 MiB (in place) accesses stay plain.
 int default_hints(int mode, int s, uint64_t array_bytes, int64_t rows) {
   const uint64_t total = array_bytes * (uint64_t)(rows > 0 ? rows : 1);
-  if (mode != kModeInplace) return total >= (32ull << 20) ? kHintStreamLoads : kHintPlain;
-  if (total < (64ull << 20)) return kHintPlain;
-  if (s == 8 && total <= kCacheBytes) return kHintStreamStores;
-  return kHintStreamLoads;
+  if (total < (mode == kModeInplace ? (64ull << 20) : (32ull << 20))) return kHintPlain;
+  if (mode == kModeInplace && s == 8 && total > (64ull << 20) && total <= (128ull << 20))
+    return kHintStreamStores;
+  if (s <= 2 && total > kCacheBytes) return kHintStreamLoads;
+  if (mode != kModeInplace && s == 4 && total > (128ull << 20) && total <= kCacheBytes)
+    return kHintStreamLoads;
+  return kHintStreamWriteThrough;
 }
 
 struct Plan {
@@ -434,6 +446,8 @@ bitrev_status_t plan_batched(int s, const bitrev_config_t* cfg, const DeviceInfo
   p->threads = threads_of(s, b, true);
   p->lds = tile_lds_bytes_for(s, b, 2);
   int per_cu = te.wg_per_cu;
+  // the built-in count belongs to the built-in tile width only
+  if (per_cu <= 0 && b == dp.b) per_cu = dp.wg_per_cu;
   if (per_cu <= 0) {
     // resident at once: LDS and threads, and the registers the kernel needs
     per_cu = resident_per_cu(p->threads, p->lds);
@@ -1072,14 +1086,16 @@ const char* bitrev_tuning_format(void) { return kTuningFormat; }
 
 bitrev_status_t bitrev_copy_ex(const void* src, void* dst, size_t bytes, int cache_hints,
                                void* stream) {
-  if (src == NULL || dst == NULL || cache_hints < 0 || cache_hints > 3)
+  if (src == NULL || dst == NULL || cache_hints < 0 || cache_hints > 4)
     return BITREV_ERROR_INVALID_VALUE;
   if (bytes == 0) return BITREV_SUCCESS;
   if (overlap(src, dst, bytes)) return BITREV_ERROR_ALIAS;
   DeviceInfo d;
   bitrev_status_t st = device_info(&d, false);
   if (st != BITREV_SUCCESS) return st;
-  const int h = cache_hints ? cache_hints - 1 : (bytes > kCacheBytes ? kHintStreamLoads : kHintPlain);
+  // streaming loads with write-through stores: the fastest form measured at
+  // 128 MiB and at 4 GiB (plain and streaming-load copies trail by 1-4%)
+  const int h = cache_hints ? cache_hints - 1 : kHintStreamWriteThrough;
   const hipError_t e = launch_copy(src, dst, bytes, (uint32_t)(d.cus * 4), h,
                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);

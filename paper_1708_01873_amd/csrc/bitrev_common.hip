@@ -120,6 +120,9 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, uint32_t grid, 
     } else if (hints == kHintStreamStores) {
       hipLaunchKernelGGL(k_copy16<kHintStreamStores>, dim3(grid), dim3(256), 0, st,
                          static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), nvec);
+    } else if (hints == kHintStreamWriteThrough) {
+      hipLaunchKernelGGL(k_copy16<kHintStreamWriteThrough>, dim3(grid), dim3(256), 0, st,
+                         static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), nvec);
     } else {
       hipLaunchKernelGGL(k_copy16<kHintPlain>, dim3(grid), dim3(256), 0, st,
                          static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), nvec);

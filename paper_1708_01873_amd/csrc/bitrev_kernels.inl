@@ -284,6 +284,7 @@ hipError_t run_dit(const DitLaunch& a, hipStream_t st) {
   const int h = VEC ? a.t.hints : kHintPlain;
   if (h == kHintStreamLoads) return run_dit_h<S, B, VEC, kHintStreamLoads>(a, st);
   if (h == kHintStreamStores) return run_dit_h<S, B, VEC, kHintStreamStores>(a, st);
+  if (h == kHintStreamWriteThrough) return run_dit_h<S, B, VEC, kHintStreamWriteThrough>(a, st);
   return run_dit_h<S, B, VEC, kHintPlain>(a, st);
 }
 
@@ -418,10 +419,14 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched(
     } else {
       const int m = k - 2 * B;
       const uint32_t y = inplace_pair_at(m, item - (uint64_t)scan[a], balanced);
+      // an array after ones shorter than 16 bytes may start off the 16-byte
+      // grid: it moves element by element between HBM and LDS, which keeps
+      // this rare path from raising the kernel's register count (74 -> 56
+      // VGPRs for complex64 at b = 6: two workgroups per CU instead of one)
       if ((reinterpret_cast<uintptr_t>(base) & 15u) == 0) {
         tile_pair_inplace<S, B, true, NT>(base, m, y, lds);
       } else {
-        tile_pair_inplace<S, B, false, NT>(base, m, y, lds);
+        tile_pair_inplace_elem<S, B, NT, 1>(base, m, y, lds);
       }
     }
     __syncthreads();
@@ -452,8 +457,8 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched_oop(
       const uint32_t y = oop_tile_at(m, local, balanced);
       if (((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0) {
         tile_outofplace<S, B, true, NT>(in, out, m, y, lds);
-      } else {
-        tile_outofplace<S, B, false, NT>(in, out, m, y, lds);
+      } else {  // element by element, as in k_batched
+        tile_outofplace_elem<S, B, NT, 1>(in, out, m, y, lds);
       }
     }
     __syncthreads();
@@ -481,6 +486,7 @@ hipError_t run_tile_inplace(const TileLaunch& a, hipStream_t st) {
   const int h = VEC ? a.hints : kHintPlain;
   if (h == kHintStreamLoads) return run_inplace_h<S, B, VEC, kHintStreamLoads>(a, st);
   if (h == kHintStreamStores) return run_inplace_h<S, B, VEC, kHintStreamStores>(a, st);
+  if (h == kHintStreamWriteThrough) return run_inplace_h<S, B, VEC, kHintStreamWriteThrough>(a, st);
   return run_inplace_h<S, B, VEC, kHintPlain>(a, st);
 }
 
@@ -502,6 +508,8 @@ hipError_t run_tile_outofplace(const TileLaunch& a, hipStream_t st) {
   const int h = VEC ? a.hints : kHintPlain;
   if (h == kHintStreamLoads) return run_outofplace_h<S, B, VEC, kHintStreamLoads>(a, st);
   if (h == kHintStreamStores) return run_outofplace_h<S, B, VEC, kHintStreamStores>(a, st);
+  if (h == kHintStreamWriteThrough)
+    return run_outofplace_h<S, B, VEC, kHintStreamWriteThrough>(a, st);
   return run_outofplace_h<S, B, VEC, kHintPlain>(a, st);
 }
 
@@ -578,6 +586,10 @@ hipError_t dispatch_digit(int b, bool vec, const TileLaunch& a, hipStream_t st) 
                              a.total_items, a.xcds);
         } else if (a.hints == kHintStreamStores) {
           hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintStreamStores>), dim3(a.grid),
+                             dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
+                             a.total_items, a.xcds);
+        } else if (a.hints == kHintStreamWriteThrough) {
+          hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintStreamWriteThrough>), dim3(a.grid),
                              dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
                              a.total_items, a.xcds);
         } else {

@@ -114,7 +114,7 @@ def plain_candidates(log2n: int, elem_size: int, mode: int) -> list[Candidate]:
             for variant in ((1, 2, 3) if mode == MODE_INPLACE else (1, 2)):
                 for xcd in (1, 2):
                     # cache hints apply to the one-item and register-staged kernels
-                    for hints in ((1, 2, 3) if variant != 2 else (0,)):
+                    for hints in ((1, 2, 3, 4) if variant != 2 else (0,)):
                         out.append(Candidate(b, order, variant, 0, xcd, hints))
     return out
 

@@ -90,7 +90,7 @@ def test_rows_validation(L):
 def test_config_validation(L):
     for cfg in (br.Config(8, 0, 0, 0), br.Config(-1, 0, 0, 0), br.Config(0, -5, 0, 0),
                 br.Config(0, 0, 4, 0), br.Config(0, 0, 0, 4), br.Config(0, 0, 0, -1),
-                br.Config(0, 0, 0, 0, 3), br.Config(0, 0, 0, 0, 0, 4), br.Config(0, 0, 0, 0, 0, -1)):
+                br.Config(0, 0, 0, 0, 3), br.Config(0, 0, 0, 0, 0, 5), br.Config(0, 0, 0, 0, 0, -1)):
         assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
 
 
@@ -136,7 +136,7 @@ def test_timed_entry_validation(L):
 
 
 def test_copy_validation(L):
-    assert L.bitrev_copy_ex(FAKE, FAKE + 64, 16, 4, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_ex(FAKE, FAKE + 64, 16, 5, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_copy_ex(FAKE, FAKE + 64, 16, -1, None) == br.ERROR_INVALID_VALUE
     assert L.bitrev_copy(FAKE, FAKE + 8, 16, None) == br.ERROR_ALIAS
     assert L.bitrev_copy(None, FAKE, 16, None) == br.ERROR_INVALID_VALUE
@@ -153,12 +153,21 @@ def test_plan_query_defaults(L):
     p = br.bitrev_plan_query(24, 8)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
     assert p["cache_hints"] == br.HINTS_STREAM_STORES
+    assert br.bitrev_plan_query(23, 8)["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
+    assert br.bitrev_plan_query(25, 8)["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
     p = br.bitrev_plan_query(28, 8)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
-    assert p["cache_hints"] == br.HINTS_STREAM_LOADS  # beyond the Infinity Cache
+    assert p["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
     assert br.bitrev_plan_query(24, 8, cache_hints=br.HINTS_PLAIN)["cache_hints"] == 1
-    assert br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)["cache_hints"] == 2
+    assert br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)["cache_hints"] == 4
     assert br.bitrev_plan_query(20, 8)["cache_hints"] == 1  # small arrays: plain
+    # 1- and 2-byte elements beyond the Infinity Cache, and float32 out of
+    # place at 256 MiB, keep streaming loads alone
+    assert br.bitrev_plan_query(29, 1)["cache_hints"] == br.HINTS_STREAM_LOADS
+    assert br.bitrev_plan_query(28, 2, mode=br.MODE_OUTOFPLACE)["cache_hints"] == 2
+    assert br.bitrev_plan_query(26, 4, mode=br.MODE_OUTOFPLACE)["cache_hints"] == 2
+    assert br.bitrev_plan_query(26, 4)["cache_hints"] == 4
+    assert br.bitrev_plan_query(27, 1)["cache_hints"] == 4
     p = br.bitrev_plan_query(24, 8, mode=br.MODE_OUTOFPLACE)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 1, 2, 1)
     assert p["work_items"] == 2**14

@@ -43,6 +43,35 @@ def test_batched_mixed_sizes(s):
             assert br.bitrev_batched_errors(ws) == (0, -1)
 
 
+@pytest.mark.parametrize("s", (1, 2, 4, 8))
+@pytest.mark.parametrize("oop", (False, True))
+def test_batched_misaligned_large_arrays(s, oop):
+    """Arrays long enough for the tile path that start off the 16-byte grid
+    (after a 1-element array): they take the element-by-element tile routine,
+    in place at every batched tile width, out of place at the default one."""
+    log2n = np.array([0, 14, 0, 0, 13, 1, 12, 0, 15, 2, 12], dtype=np.int32)
+    offsets = np.concatenate([[0], np.cumsum(1 << log2n.astype(np.int64))]).astype(np.int64)
+    assert any((int(o) * s) % 16 for o, k in zip(offsets[:-1], log2n) if k >= 12)
+    host = workloads.byte_pattern(int(offsets[-1]) * s, seed=70 + s)
+    want = host.copy()
+    oracle.batched(want, offsets, log2n, s)
+    # out of place has no config: its default plan only
+    for b in ((0,) if oop else range(2, {1: 7, 2: 7, 4: 7, 8: 6}[s] + 1)):
+        x = to_device(host, s)
+        off, l2 = _meta(offsets, log2n)
+        ws = torch.empty(br.bitrev_batched_workspace_size(len(log2n)), dtype=torch.uint8,
+                         device="cuda")
+        if oop:
+            y = torch.empty_like(x)
+            br.bitrev_batched_outofplace(x, y, off, l2, ws)
+            got = to_host_bytes(y)
+        else:
+            br.bitrev_batched(x, off, l2, ws, tile_bits=b)
+            got = to_host_bytes(x)
+        assert_bytes_equal(got, want, "misaligned batched s=%d b=%d oop=%s" % (s, b, oop))
+        assert br.bitrev_batched_errors(ws) == (0, -1)
+
+
 def test_batched_default_plan_and_grids():
     offsets, log2n = workloads.batched_layout(300, 0, 18, seed=5)
     host = workloads.byte_pattern(int(offsets[-1]) * 8, seed=9)

@@ -73,6 +73,21 @@ def test_dit_forced_tile_widths(dtype):
             _check(to_host_bytes(t).view(dtype), x, L, False, dtype)
 
 
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_dit_cache_hints(dtype):
+    """Every cache-hint instance of the fused kernel, in and out of place."""
+    k = 16
+    for hints in (br.HINTS_PLAIN, br.HINTS_STREAM_LOADS, br.HINTS_STREAM_STORES,
+                  br.HINTS_STREAM_WRITE_THROUGH):
+        for L in (1, 4):
+            x = _data(k, 1, dtype, 1000 + 10 * hints + L)
+            t = torch.from_numpy(x).cuda()
+            y = br.bitrev_dit_stages(t, stages=L, cache_hints=hints)
+            _check(to_host_bytes(y).view(dtype), x, L, False, dtype)
+            br.bitrev_dit_stages(t, t, stages=L, cache_hints=hints)
+            _check(to_host_bytes(t).view(dtype), x, L, False, dtype)
+
+
 def test_dit_rows_and_full_size():
     """Many rows, and the complex64 2^24 array at six fused levels."""
     x = _data(12, 9, np.complex64, 3).reshape(9, 1 << 12)

@@ -116,12 +116,13 @@ def test_element_aligned_wide_tiles(s):
 def test_cache_hints(s):
     """Every cache-hint instance of the one-item tile kernels and of the
     register-staged in-place kernel (plain, streaming loads, streaming
-    stores), every order, in and out of place, 16-byte and per-element
+    stores, streaming loads with write-through stores), every order, in and out of place, 16-byte and per-element
     access, against the oracle."""
     for k in (13, 16):
         host = workloads.byte_pattern((1 << k) * s, seed=31 * s + k)
         want = oracle.outofplace(host, s)
-        for hints in (br.HINTS_PLAIN, br.HINTS_STREAM_LOADS, br.HINTS_STREAM_STORES):
+        for hints in (br.HINTS_PLAIN, br.HINTS_STREAM_LOADS, br.HINTS_STREAM_STORES,
+                      br.HINTS_STREAM_WRITE_THROUGH):
             for inplace, variant in ((True, 1), (True, 3), (False, 1)):
                 for order in (1, 2, 3):
                     for pad in (0, 1):
@@ -187,7 +188,7 @@ def test_copy_hints():
     for nbytes in (1 << 20, (1 << 20) + 7):
         host = workloads.byte_pattern(nbytes, seed=nbytes)
         x = torch.from_numpy(host).cuda()
-        for hints in (0, 1, 2, 3):
+        for hints in (0, 1, 2, 3, 4):
             y = torch.zeros_like(x)
             br.bitrev_copy(x, y, cache_hints=hints)
             assert_bytes_equal(y.cpu().numpy(), host, "copy hints=%d n=%d" % (hints, nbytes))
