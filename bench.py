@@ -134,6 +134,24 @@ def cpu_baseline(host, target_s: float = 10.0, max_reps: int = 20):
     return reps, el, ok
 
 
+def cpu_multicore(host, target_s: float = 5.0, max_reps: int = 40):
+    """The oracle's out-of-place permutation of the same array with its index
+    range split over the host's OpenMP threads, repeated until about target_s
+    seconds have run: the CPU on all its cores, next to the one-core figure."""
+    import numpy as np
+    import oracle
+    reps, threads, out = 0, 0, None
+    t0 = time.perf_counter()
+    while True:
+        out, threads = oracle.outofplace_mt(host)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or reps >= max_reps:
+            break
+    ok = np.array_equal(out.view(np.uint8), oracle.outofplace(host).view(np.uint8))
+    return reps, el, threads, ok
+
+
 def batched_speedup(torch, br, reps: int):
     """4096 complex64 arrays, log2 n uniform in [8, 20] (seed 5): one replay
     of the captured batched launch vs an eager loop of per-array in-place
@@ -491,6 +509,16 @@ def main() -> int:
             "bit_exact_vs_oracle_outofplace": ok,
             "cpu_model": cpu_model(),
             "host_cores_available": len(os.sched_getaffinity(0)),
+        }
+        log("cpu baseline: oracle out of place over all host threads")
+        reps, el, threads, ok = cpu_multicore(host)
+        out["cpu_baseline"]["all_cores"] = {
+            "value": round(gbs(nbytes * reps, el * 1e3), 4),
+            "unit": "GB/s",
+            "cores": threads,
+            "kind": "oracle, out of place, index range split over OpenMP threads",
+            "sample": "the full 2^24 complex64 array, %d repetitions in %.1f s" % (reps, el),
+            "bit_exact_vs_oracle_outofplace": ok,
         }
     print(json.dumps(out), flush=True)
     return 0

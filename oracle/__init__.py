@@ -25,7 +25,7 @@ def compile_source(src: str, out: str) -> str:
     """Compile an oracle C source into a shared library at ``out``."""
     tmp = out + ".tmp%d" % os.getpid()
     subprocess.check_call(
-        ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared",
+        ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-fopenmp", "-fPIC", "-shared",
          src, "-o", tmp])
     os.replace(tmp, out)
     return out
@@ -62,6 +62,9 @@ class Oracle:
         L.oracle_outofplace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                         ctypes.c_size_t]
         L.oracle_outofplace.restype = ctypes.c_int
+        L.oracle_outofplace_mt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_size_t]
+        L.oracle_outofplace_mt.restype = ctypes.c_int
         L.oracle_rows.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                   ctypes.c_int64, ctypes.c_size_t]
         L.oracle_rows.restype = ctypes.c_int
@@ -114,6 +117,18 @@ class Oracle:
         if self.lib.oracle_outofplace(a.ctypes.data, out.ctypes.data, k, s) != 0:
             raise ValueError("oracle_outofplace rejected its arguments")
         return out
+
+    def outofplace_mt(self, a: np.ndarray, elem_size: int | None = None):
+        """outofplace with the index range split over the host's OpenMP
+        threads, for timing the CPU baseline on all cores.  Returns
+        (dst, threads used)."""
+        s, n = self._elems(a, elem_size)
+        k = _log2_exact(n)
+        out = np.empty_like(a)
+        t = self.lib.oracle_outofplace_mt(a.ctypes.data, out.ctypes.data, k, s)
+        if t < 1:
+            raise ValueError("oracle_outofplace_mt rejected its arguments")
+        return out, t
 
     def rows(self, a: np.ndarray, k: int, elem_size: int | None = None,
              inplace: bool = False) -> np.ndarray:
@@ -196,6 +211,10 @@ def inplace(a, elem_size=None):
 
 def outofplace(a, elem_size=None):
     return default().outofplace(a, elem_size)
+
+
+def outofplace_mt(a, elem_size=None):
+    return default().outofplace_mt(a, elem_size)
 
 
 def rows(a, k, elem_size=None, inplace=False):

@@ -34,6 +34,7 @@
  * generator, the even-odd (Stockham) chain, the recursive square-transpose
  * decomposition and the swap-count closed form.
  */
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <string.h>
@@ -95,6 +96,33 @@ int oracle_outofplace(const void *src, void *dst, int k, size_t elem_size)
     for (i = 0; i < n; ++i)
         memcpy(out + oracle_rev(i, k) * elem_size, in + i * elem_size, elem_size);
     return 0;
+}
+
+/* The same out-of-place definition with the index range split over the host
+ * threads (OpenMP, static schedule): every i is still visited exactly once and
+ * dest[rev(i)] <- src[i] with the bitwise rev above, so the result is
+ * oracle_outofplace's.  It exists only to time the CPU baseline on all host
+ * cores.  Returns the number of threads used, or -1 for an argument outside
+ * the domain. */
+int oracle_outofplace_mt(const void *src, void *dst, int k, size_t elem_size)
+{
+    const unsigned char *in = (const unsigned char *)src;
+    unsigned char *out = (unsigned char *)dst;
+    int64_t n;
+    int threads = 1;
+    if (k < 0 || k > ORACLE_MAX_LOG2N || elem_size == 0 || src == NULL || dst == NULL)
+        return -1;
+    n = (int64_t)1 << k;
+#pragma omp parallel
+    {
+#pragma omp single
+        threads = omp_get_num_threads();
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            memcpy(out + oracle_rev((uint64_t)i, k) * elem_size, in + (uint64_t)i * elem_size,
+                   elem_size);
+    }
+    return threads;
 }
 
 /* `rows` independent arrays of 2^k elements each, stored one after another.

@@ -162,6 +162,22 @@ def pin_element_sizes(o) -> None:
             assert np.array_equal(ip, want), (s, k)
 
 
+def pin_outofplace_threads(o) -> None:
+    """The multi-threaded out-of-place form (CPU-baseline timing only) gives
+    the byte-table permutation, for sizes that split unevenly over threads."""
+    rng = np.random.default_rng(16)
+    for s in (1, 3, 8, 16):
+        for k in (0, 1, 2, 5, 9, 13):
+            n = 1 << k
+            buf = rng.integers(0, 256, size=n * s, dtype=np.uint8)
+            perm = np.array([rev_bytetable(j, k) for j in range(n)], dtype=np.int64)
+            want = np.empty_like(buf).reshape(n, s)
+            want[perm] = buf.reshape(n, s)
+            got, threads = o.outofplace_mt(buf, s)
+            assert threads >= 1
+            assert np.array_equal(got, want.reshape(-1)), (s, k)
+
+
 def pin_special_values(o) -> None:
     """NaN payloads, signed zeros and infinities move as bits."""
     vals = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.5, 5e-324, 1e308], dtype=np.float64)
@@ -269,6 +285,7 @@ def pin_digit_reversal(o) -> None:
 
 
 ALL_PINS.append(pin_digit_reversal)
+ALL_PINS.append(pin_outofplace_threads)
 
 
 def pin_evenodd_split(o) -> None:
