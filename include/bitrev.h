@@ -293,6 +293,18 @@ bitrev_status_t bitrev_digitrev_inplace(void* data, int log2n, int digit_bits, s
                                         void* stream);
 bitrev_status_t bitrev_digitrev_outofplace(const void* src, void* dst, int log2n, int digit_bits,
                                            size_t elem_size, void* stream);
+/* With a launch configuration (NULL = library choice): tile_bits must be a
+ * multiple of digit_bits (else BITREV_ERROR_NOT_SUPPORTED, as for a width
+ * that is not compiled or does not fit); order sets the source-tile order out
+ * of place (in place the pairs follow the grouped digit order); grid_blocks,
+ * xcd_remap and cache_hints as in bitrev_config_t; variant is ignored.  A
+ * config field out of range returns BITREV_ERROR_INVALID_VALUE. */
+bitrev_status_t bitrev_digitrev_inplace_ex(void* data, int log2n, int digit_bits,
+                                           size_t elem_size, const bitrev_config_t* cfg,
+                                           void* stream);
+bitrev_status_t bitrev_digitrev_outofplace_ex(const void* src, void* dst, int log2n,
+                                              int digit_bits, size_t elem_size,
+                                              const bitrev_config_t* cfg, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Bit reversal fused with the first FFT levels                              */

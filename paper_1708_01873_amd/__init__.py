@@ -89,6 +89,8 @@ _SIGNATURES = {
     "bitrev_plan_query": ([_I, _SZ, _I64, _I, _CFGP, ctypes.POINTER(Plan)], _I),
     "bitrev_load_tuning": ([ctypes.c_char_p], _I),
     "bitrev_tuning_format": ([], ctypes.c_char_p),
+    "bitrev_digitrev_inplace_ex": ([_VP, _I, _I, _SZ, _CFGP, _VP], _I),
+    "bitrev_digitrev_outofplace_ex": ([_VP, _VP, _I, _I, _SZ, _CFGP, _VP], _I),
     "bitrev_copy": ([_VP, _VP, _SZ, _VP], _I),
     "bitrev_copy_ex": ([_VP, _VP, _SZ, _I, _VP], _I),
     "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
@@ -443,19 +445,29 @@ def bitrev_copy(src, dst, stream=None, *, cache_hints=0):
     return dst
 
 
-def bitrev_digitrev_inplace(data, digit_bits: int, log2n: Optional[int] = None, *, stream=None):
+def bitrev_digitrev_inplace(data, digit_bits: int, log2n: Optional[int] = None, *, tile_bits=0,
+                            grid_blocks=0, order=0, xcd_remap=0, cache_hints=0, config=None,
+                            stream=None):
     """Reverse the order of the digit_bits-bit digits of every index, in place
-    (digit_bits 2: radix-4 order, 3: radix-8 order, 1: bit reversal)."""
+    (digit_bits 2: radix-4 order, 3: radix-8 order, 1: bit reversal).  The
+    keyword arguments force the launch configuration (bitrev_digitrev_inplace_ex)."""
     ptr, s = _tensor_args(data, "data")
     k = _log2_exact(data.numel()) if log2n is None else int(log2n)
-    _check(_load().bitrev_digitrev_inplace(ptr, k, int(digit_bits), s, _stream(stream)),
-           "bitrev_digitrev_inplace")
+    cfg = _config(tile_bits, grid_blocks, order, config, 0, xcd_remap, cache_hints)
+    if cfg is None:
+        st = _load().bitrev_digitrev_inplace(ptr, k, int(digit_bits), s, _stream(stream))
+    else:
+        st = _load().bitrev_digitrev_inplace_ex(ptr, k, int(digit_bits), s, ctypes.byref(cfg),
+                                                _stream(stream))
+    _check(st, "bitrev_digitrev_inplace")
     return data
 
 
 def bitrev_digitrev_outofplace(src, dst=None, digit_bits: int = 2, log2n: Optional[int] = None, *,
-                               stream=None):
-    """dst[drev(i)] = src[i] for digits of digit_bits bits."""
+                               tile_bits=0, grid_blocks=0, order=0, xcd_remap=0, cache_hints=0,
+                               config=None, stream=None):
+    """dst[drev(i)] = src[i] for digits of digit_bits bits.  The keyword
+    arguments force the launch configuration (bitrev_digitrev_outofplace_ex)."""
     if dst is None:
         import torch
         dst = torch.empty_like(src)
@@ -464,8 +476,13 @@ def bitrev_digitrev_outofplace(src, dst=None, digit_bits: int = 2, log2n: Option
     if s != s2 or src.numel() != dst.numel():
         raise ValueError("src and dst must have the same element size and length")
     k = _log2_exact(src.numel()) if log2n is None else int(log2n)
-    _check(_load().bitrev_digitrev_outofplace(sp, dp, k, int(digit_bits), s, _stream(stream)),
-           "bitrev_digitrev_outofplace")
+    cfg = _config(tile_bits, grid_blocks, order, config, 0, xcd_remap, cache_hints)
+    if cfg is None:
+        st = _load().bitrev_digitrev_outofplace(sp, dp, k, int(digit_bits), s, _stream(stream))
+    else:
+        st = _load().bitrev_digitrev_outofplace_ex(sp, dp, k, int(digit_bits), s,
+                                                   ctypes.byref(cfg), _stream(stream))
+    _check(st, "bitrev_digitrev_outofplace")
     return dst
 
 

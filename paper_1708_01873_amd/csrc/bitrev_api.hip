@@ -662,17 +662,21 @@ hipError_t launch_wave_digit(int s, const WaveLaunch& a, int d, hipStream_t st) 
 }
 
 // Digit-reversed permutation (d-bit digits) of one array; src == dst in place.
-bitrev_status_t run_digit(const void* src, void* dst, int k, int d, size_t s, void* stream) {
+// cfg (may be NULL): tile_bits (a whole number of digits), grid_blocks,
+// order (out of place: the source tile order; in place the grouped digit
+// order is fixed), xcd_remap and cache_hints as for the plain calls.
+bitrev_status_t run_digit(const void* src, void* dst, int k, int d, size_t s,
+                          const bitrev_config_t* cfg, void* stream) {
   // ---- validation: no HIP call before this block completes ----
   if (src == NULL || dst == NULL || k < 0 || k > BITREV_MAX_LOG2N || !valid_elem_size(s) ||
-      d < 1 || d > 3 || k % d)
+      d < 1 || d > 3 || k % d || !valid_config(cfg))
     return BITREV_ERROR_INVALID_VALUE;
   if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % s)
     return BITREV_ERROR_INVALID_VALUE;
   const uint64_t n = 1ull << k;
   const bool inplace = (src == dst);
   if (!inplace && overlap(src, dst, (size_t)(n * s))) return BITREV_ERROR_ALIAS;
-  if (d == 1) return run_plain(src, dst, k, 1, s, NULL, stream);
+  if (d == 1) return run_plain(src, dst, k, 1, s, cfg, stream);
   if (inplace && k <= d) return BITREV_SUCCESS;  // one digit: the identity
   // ---- plan and launch ----
   DeviceInfo dev;
@@ -692,14 +696,21 @@ bitrev_status_t run_digit(const void* src, void* dst, int k, int d, size_t s, vo
   }
   const DefaultPlan dp = default_plan(inplace ? 0 : 1, (int)s, n * s);
   int b = dp.b;
-  // b must be a multiple of d: round up where the element size and the
-  // array allow (radix 8 out of place, complex64 2^24: b = 3 moved 2.2 TB/s)
-  const int bu = (b + d - 1) / d * d;
-  if (bu <= max_tile_bits((int)s) && 2 * bu <= k) b = bu;
-  if (b > max_tile_bits((int)s)) b = max_tile_bits((int)s);
-  if (2 * b > k) b = k / 2;
-  b -= b % d;
-  while (b >= d && tile_lds_bytes_for((int)s, b, inplace ? 2 : 2) > dev.lds_per_block) b -= d;
+  if (cfg && cfg->tile_bits) {
+    b = cfg->tile_bits;  // forced: whole digits, within the array, compiled, fits
+    if (b % d || 2 * b > k || b > max_tile_bits((int)s) ||
+        tile_lds_bytes_for((int)s, b, 2) > dev.lds_per_block)
+      return BITREV_ERROR_NOT_SUPPORTED;
+  } else {
+    // b must be a multiple of d: round up where the element size and the
+    // array allow (radix 8 out of place, complex64 2^24: b = 3 moved 2.2 TB/s)
+    const int bu = (b + d - 1) / d * d;
+    if (bu <= max_tile_bits((int)s) && 2 * bu <= k) b = bu;
+    if (b > max_tile_bits((int)s)) b = max_tile_bits((int)s);
+    if (2 * b > k) b = k / 2;
+    b -= b % d;
+    while (b >= d && tile_lds_bytes_for((int)s, b, 2) > dev.lds_per_block) b -= d;
+  }
   if (b < d) return BITREV_ERROR_NOT_SUPPORTED;
   const int m = k - 2 * b;
   if (m > 32) return BITREV_ERROR_NOT_SUPPORTED;
@@ -710,10 +721,21 @@ bitrev_status_t run_digit(const void* src, void* dst, int k, int d, size_t s, vo
   a.total_items = inplace ? dpair_count(m, d) : (1ull << m);
   a.items_per_seg = a.total_items;
   a.seg_elems = n;
-  a.balanced = 0;
-  a.xcds = dp.xcd_remap == 2 ? 1 : dev.xcds;
-  a.grid = default_grid(a.total_items, dev);
-  a.hints = default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, 1);
+  // complex64 out of place at b = 6 measured otherwise at 2^24 (eight
+  // alternating rounds): streaming loads rather than write-through stores,
+  // and for radix 4 the grouped tile order in dispatch order (radix 4
+  // 5236 -> 5547 GB/s, radix 8 5670 -> 5760)
+  const bool c64_oop6 = !inplace && s == 8 && b == 6;
+  a.balanced = (cfg && cfg->order) ? order_code(cfg->order) : ((c64_oop6 && d == 2) ? order_code(3) : 0);
+  const int xr = (cfg && cfg->xcd_remap) ? cfg->xcd_remap : ((c64_oop6 && d == 2) ? 2 : dp.xcd_remap);
+  a.xcds = xr == 2 ? 1 : dev.xcds;
+  a.grid = (cfg && cfg->grid_blocks > 0) ? round_up((uint64_t)cfg->grid_blocks, (uint32_t)dev.xcds)
+                                         : default_grid(a.total_items, dev);
+  a.hints = (cfg && cfg->cache_hints)
+                ? cfg->cache_hints - 1
+                : default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, 1);
+  if (!(cfg && cfg->cache_hints) && c64_oop6 && a.hints == kHintStreamWriteThrough)
+    a.hints = kHintStreamLoads;
   a.pipelined = 0;
   const size_t vb = (s << b) < 16 ? (s << b) : 16;
   e = launch_digit((int)s, d, b, pointer_align(src, dst) % vb == 0, a, hs);
@@ -726,13 +748,26 @@ extern "C" {
 
 bitrev_status_t bitrev_digitrev_inplace(void* data, int log2n, int digit_bits, size_t elem_size,
                                         void* stream) {
-  return run_digit(data, data, log2n, digit_bits, elem_size, stream);
+  return run_digit(data, data, log2n, digit_bits, elem_size, NULL, stream);
 }
 
 bitrev_status_t bitrev_digitrev_outofplace(const void* src, void* dst, int log2n, int digit_bits,
                                            size_t elem_size, void* stream) {
   if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;
-  return run_digit(src, dst, log2n, digit_bits, elem_size, stream);
+  return run_digit(src, dst, log2n, digit_bits, elem_size, NULL, stream);
+}
+
+bitrev_status_t bitrev_digitrev_inplace_ex(void* data, int log2n, int digit_bits,
+                                           size_t elem_size, const bitrev_config_t* cfg,
+                                           void* stream) {
+  return run_digit(data, data, log2n, digit_bits, elem_size, cfg, stream);
+}
+
+bitrev_status_t bitrev_digitrev_outofplace_ex(const void* src, void* dst, int log2n,
+                                              int digit_bits, size_t elem_size,
+                                              const bitrev_config_t* cfg, void* stream) {
+  if (src != NULL && src == dst) return BITREV_ERROR_ALIAS;
+  return run_digit(src, dst, log2n, digit_bits, elem_size, cfg, stream);
 }
 
 uint32_t bitrev_debug_digit_rev(uint32_t v, int j, int d) {

@@ -304,7 +304,7 @@ hipError_t dispatch_dit(int b, bool vec, const DitLaunch& a, hipStream_t st) {
 // whole numbers of digits, so drev([x | y | z]) = [drev(z) | drev(y) | drev(x)].
 template <int S, int B, int D, bool VEC, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_digit(
-    const void* src, void* dst, int m, uint64_t total_items, int xcds) {
+    const void* src, void* dst, int m, uint64_t total_items, int order, int xcds) {
   static_assert(B % D == 0, "the tile width must be a whole number of digits");
   typedef typename Bytes<S>::T E;
   typedef TileShape<S, B, VEC> Sh;
@@ -317,7 +317,9 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_digit(
   E* out = static_cast<E*>(dst);
   for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
     Chunk<S, Sh::VB> ra[PT], rb[PT];
-    const uint32_t y = inplace ? dinplace_pair_at(m, item, D) : (uint32_t)item;
+    // out of place any order of the source tiles works (each lands on its
+    // own destination tile); the order code as for the bit-reversal kernels
+    const uint32_t y = inplace ? dinplace_pair_at(m, item, D) : oop_tile_at(m, (uint32_t)item, order);
     const uint32_t yr = drev_bits(y, m, D);
     const bool two = inplace && (y != yr);
     tile_load<S, B, VEC, NT, PT, H>(ra, in, rowstride, y);
@@ -586,24 +588,24 @@ hipError_t dispatch_digit(int b, bool vec, const TileLaunch& a, hipStream_t st) 
         if (a.hints == kHintStreamLoads) {
           hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintStreamLoads>), dim3(a.grid),
                              dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
-                             a.total_items, a.xcds);
+                             a.total_items, a.balanced, a.xcds);
         } else if (a.hints == kHintStreamStores) {
           hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintStreamStores>), dim3(a.grid),
                              dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
-                             a.total_items, a.xcds);
+                             a.total_items, a.balanced, a.xcds);
         } else if (a.hints == kHintStreamWriteThrough) {
           hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintStreamWriteThrough>), dim3(a.grid),
                              dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
-                             a.total_items, a.xcds);
+                             a.total_items, a.balanced, a.xcds);
         } else {
           hipLaunchKernelGGL((k_tile_digit<S, B, D, true, kHintPlain>), dim3(a.grid),
                              dim3(tile_threads<S, B, true>()), 0, st, a.src, a.dst, a.m,
-                             a.total_items, a.xcds);
+                             a.total_items, a.balanced, a.xcds);
         }
       } else {
         hipLaunchKernelGGL((k_tile_digit<S, B, D, false, kHintPlain>), dim3(a.grid),
                            dim3(tile_threads<S, B, false>()), 0, st, a.src, a.dst, a.m,
-                           a.total_items, a.xcds);
+                           a.total_items, a.balanced, a.xcds);
       }
       return hipGetLastError();
     }

@@ -94,6 +94,19 @@ def test_config_validation(L):
         assert L.bitrev_inplace_ex(FAKE, 20, 8, ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
 
 
+def test_digit_config_validation(L):
+    """The configurable digit-reversal entries reject a config field out of
+    range before any HIP call, in and out of place."""
+    for cfg in (br.Config(8, 0, 0, 0), br.Config(0, -5, 0, 0), br.Config(0, 0, 4, 0),
+                br.Config(0, 0, 0, 0, 3), br.Config(0, 0, 0, 0, 0, 5)):
+        assert L.bitrev_digitrev_inplace_ex(FAKE, 20, 2, 8, ctypes.byref(cfg), None) == \
+            br.ERROR_INVALID_VALUE
+        assert L.bitrev_digitrev_outofplace_ex(FAKE, FAKE + (1 << 30), 20, 2, 8,
+                                               ctypes.byref(cfg), None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_digitrev_outofplace_ex(FAKE, FAKE, 20, 2, 8, None, None) == br.ERROR_ALIAS
+    assert L.bitrev_digitrev_inplace_ex(FAKE, 21, 2, 8, None, None) == br.ERROR_INVALID_VALUE
+
+
 def test_batched_validation(L):
     ws = br.bitrev_batched_workspace_size(4096)
     assert ws >= (4096 + 3) * 8 and ws % 256 == 0

@@ -46,6 +46,32 @@ def test_digitrev_complex64_2p24():
             assert_bytes_equal(to_host_bytes(x), want, "%s digits d=%d ip" % (name, d))
 
 
+@pytest.mark.parametrize("s", (4, 8, 16))
+def test_digitrev_forced_configs(s):
+    """The configurable entries: every tile width that is a whole number of
+    digits, every out-of-place tile order and XCD mapping, each cache hint;
+    a width that is not a whole number of digits is refused."""
+    for d, k in ((2, 16), (3, 18)):
+        host = workloads.byte_pattern((1 << k) * s, seed=7 * s + d)
+        want = oracle.digit_outofplace(host, d, s)
+        for b in range(d, 7 if s < 16 else 6, d):
+            for order in (1, 2, 3):
+                for xcd, hints in ((1, 1), (2, 4), (1, 2), (2, 3)):
+                    x = to_device(host, s)
+                    y = br.bitrev_digitrev_outofplace(x, None, d, k, tile_bits=b, order=order,
+                                                      xcd_remap=xcd, cache_hints=hints)
+                    assert_bytes_equal(to_host_bytes(y), want, "oop s=%d d=%d b=%d o=%d x=%d h=%d"
+                                       % (s, d, b, order, xcd, hints))
+                    if order == 1:
+                        br.bitrev_digitrev_inplace(x, d, k, tile_bits=b, xcd_remap=xcd,
+                                                   cache_hints=hints)
+                        assert_bytes_equal(to_host_bytes(x), want, "ip s=%d d=%d b=%d x=%d h=%d"
+                                           % (s, d, b, xcd, hints))
+        with pytest.raises(br.BitrevError) as e:
+            br.bitrev_digitrev_inplace(to_device(host, s), d, k, tile_bits=d + 1)
+        assert e.value.status == br.ERROR_NOT_SUPPORTED
+
+
 def test_digitrev_misaligned_and_errors():
     host = workloads.byte_pattern((1 << 14) * 4, seed=5)
     want = oracle.digit_outofplace(host, 2, 4)
