@@ -183,6 +183,24 @@ def test_timing_events():
         ka.destroy()  # a second destroy is a no-op
 
 
+@pytest.mark.parametrize("s", (1, 2, 4))
+def test_write_through_narrow_rows(s):
+    """Write-through stores on tile rows narrower than 16 bytes: the 8-, 4-,
+    2- and 1-byte store forms of that cache hint, in and out of place, for
+    every narrow tile width, one item per workgroup and register-staged
+    (8-byte elements have no row narrower than 16 bytes)."""
+    k = 12
+    host = workloads.byte_pattern((1 << k) * s, seed=90 + s)
+    want = oracle.outofplace(host, s)
+    for b in range(1, 6):
+        if (s << b) >= 16:
+            break
+        for inplace, variant in ((True, 1), (True, 3), (False, 1)):
+            got = _run(host, k, s, inplace, tile_bits=b, variant=variant,
+                       cache_hints=br.HINTS_STREAM_WRITE_THROUGH)
+            assert_bytes_equal(got, want, "s=%d b=%d ip=%s v=%d" % (s, b, inplace, variant))
+
+
 def test_copy_hints():
     """The reference copy with each cache hint copies every byte."""
     for nbytes in (1 << 20, (1 << 20) + 7):
