@@ -220,6 +220,17 @@ def test_plan_query_defaults(L):
     assert q["variant"] == br.VARIANT_ONE_ITEM
 
 
+def test_rows_plan_class_is_the_launch_footprint(L):
+    """A launch of many short rows takes the plan class of its whole
+    footprint: 256 rows of 2^16 float32 (64 MiB) get the one-item kernel with
+    write-through stores, one such row (256 KiB) the small-array class."""
+    many = br.bitrev_plan_query(16, 4, rows=256, mode=br.MODE_OUTOFPLACE)
+    assert (many["variant"], many["order"], many["cache_hints"]) == (1, 1, 4)
+    assert many["work_items"] == 256 * 2**4
+    one = br.bitrev_plan_query(16, 4, rows=1, mode=br.MODE_OUTOFPLACE)
+    assert (one["variant"], one["cache_hints"]) == (2, 1)
+
+
 def test_tuning_file(L, tmp_path):
     good = tmp_path / "tune.txt"
     good.write_text("# comment\n\ninplace 8 24 5 0 2 1 2   # trailing comment\n"
