@@ -414,8 +414,11 @@ def main() -> int:
         kernel = "k_tile_inplace<8,%d,true,%d>" % (plan["tile_bits"], plan["cache_hints"] - 1)
     traffic = read_traffic(kernel)
     out = {
-        "metric": "effective GB/s (2*n*elem_size/time) of the in-place bit-reversed permutation",
+        "metric": "effective GB/s and % of HBM peak per n; batched vs per-array-loop speedup",
         "value": round(value, 2),
+        "value_is": "effective GB/s (2*n*elem_size/time) of the in-place bit-reversed "
+                    "permutation, complex64 n=2^24; % of HBM peak in pct_hbm_peak, the batched "
+                    "speedup in batched_speedup_vs_loop",
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -493,6 +496,7 @@ def main() -> int:
         try:
             extras["batched"] = batched_speedup(torch, br, reps=5)
             log("batched: %s" % json.dumps(extras["batched"]))
+            out["batched_speedup_vs_loop"] = round(extras["batched"]["speedup_vs_eager_loop"], 3)
         except torch.cuda.OutOfMemoryError as e:  # pragma: no cover
             extras["batched"] = {"error": str(e)}
         out["context"] = extras
