@@ -93,10 +93,9 @@ typedef struct bitrev_config {
                     * there); applies to the one-item and register-staged
                     * tile kernels with 16-byte accesses, otherwise plain.
                     * The choice: plain below 32 MiB out of place and 64 MiB
-                    * in place; streaming stores for 8-byte elements in
-                    * place above 64 MiB up to 128 MiB; streaming loads for
-                    * 1- and 2-byte elements beyond 256 MiB and for 4-byte
-                    * elements out of place at 128-256 MiB; 4 otherwise */
+                    * in place; streaming loads for 1- and 2-byte elements
+                    * beyond 256 MiB and for 4-byte elements out of place
+                    * at 128-256 MiB; 4 otherwise */
 } bitrev_config_t;
 
 /* Which code path and geometry a call uses (bitrev_plan_query). */

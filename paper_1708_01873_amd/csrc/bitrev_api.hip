@@ -208,7 +208,12 @@ DefaultPlan default_plan(int mode, int s, uint64_t array_bytes) {
       case 1: return {7, 1, 2, small ? 2 : 1};
       case 2: return {7, 1, 3, 2};
       case 4: return mid ? DefaultPlan{6, 1, 3, 2} : DefaultPlan{6, 2, 2, 1};
-      case 8: return {6, 1, 3, 2};
+      // complex64 above 64 MiB up to 128 MiB: b = 5 in natural order with
+      // write-through stores (2^24: 5816 -> 5990 GB/s per call, ranges
+      // apart over eight alternating rounds; it loses 3-12% from 256 MiB up)
+      case 8: return (array_bytes > (64ull << 20) && array_bytes <= (128ull << 20))
+                         ? DefaultPlan{5, 1, 1, 2}
+                         : DefaultPlan{6, 1, 3, 2};
       default:
         // complex128 of 128-512 MiB: the register-staged kernel (twice the
         // pairs in flight), balanced up to 256 MiB, grouped at 512 MiB
@@ -308,17 +313,15 @@ constexpr uint64_t kCacheBytes = 256ull << 20;
 // bytes) and array sizes (64 MiB - 4 GiB) on random data.  Streaming loads
 // with write-through stores were the best or tied form almost everywhere:
 // complex64 in place +4.5% at 64 MiB and +7.7% at 256 MiB over streaming
-// stores; out of place +3-6%; complex128 and float32 +1-5%.  Complex64 in
-// place of 64-128 MiB keeps streaming stores (at 128 MiB 0.5% faster per
-// call and 1% per kernel, ten alternating rounds).  Streaming loads alone
+// stores; out of place +3-6%; complex128 and float32 +1-5%; complex64 in
+// place at 128 MiB on its b = 5 plan +13% over streaming stores.  Streaming
+// loads alone
 // stay where they measured ahead: 1- and 2-byte elements beyond the Infinity
 // Cache (out of place +15%) and float32 out of place at 256 MiB (+4%).
 // Below 32 MiB (out of place) or 64 MiB (in place) accesses stay plain.
 int default_hints(int mode, int s, uint64_t array_bytes, int64_t rows) {
   const uint64_t total = array_bytes * (uint64_t)(rows > 0 ? rows : 1);
   if (total < (mode == kModeInplace ? (64ull << 20) : (32ull << 20))) return kHintPlain;
-  if (mode == kModeInplace && s == 8 && total > (64ull << 20) && total <= (128ull << 20))
-    return kHintStreamStores;
   if (s <= 2 && total > kCacheBytes) return kHintStreamLoads;
   if (mode != kModeInplace && s == 4 && total > (128ull << 20) && total <= kCacheBytes)
     return kHintStreamLoads;
@@ -850,13 +853,18 @@ bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int6
   a.t.seg_elems = n;
   // grouped pairs in place, balanced tiles out of place; the XCD mapping and
   // cache hints of the plain kernel for this size.  Complex64 measured
-  // otherwise at 2^24 (eight alternating rounds): in place at b = 5 the
-  // natural order with write-through stores (1-5 levels +3.4-3.9%), out of
-  // place at b = 6 the grouped order in dispatch order (+1.5%)
+  // otherwise (alternating rounds at 2^24-2^26): in place at b = 5 the
+  // natural order up to 128 MiB (1-5 levels at 2^24 +3.4-3.9%; grouped is
+  // 5-6% ahead at 256-512 MiB) with write-through stores; in place at b = 6
+  // streaming loads (best or tied at every size); out of place at b = 6 the
+  // grouped order in dispatch order (+1.5% at 2^24)
+  const uint64_t footprint = n * s * (uint64_t)rows;
   const bool c64_ip5 = inplace && s == 8 && b == 5;
+  const bool c64_ip6 = inplace && s == 8 && b == 6;
   const bool c64_oop6 = !inplace && s == 8 && b == 6;
+  const bool natural_ip5 = c64_ip5 && footprint <= (128ull << 20);
   a.t.balanced = order_code((cfg && cfg->order) ? cfg->order
-                                                : (c64_ip5 ? 1 : ((inplace || c64_oop6) ? 3 : 2)));
+                                                : (natural_ip5 ? 1 : ((inplace || c64_oop6) ? 3 : 2)));
   const int xr = (cfg && cfg->xcd_remap) ? cfg->xcd_remap : (c64_oop6 ? 2 : dp.xcd_remap);
   a.t.xcds = xr == 2 ? 1 : d.xcds;
   a.t.grid = (cfg && cfg->grid_blocks > 0) ? round_up((uint64_t)cfg->grid_blocks, (uint32_t)d.xcds)
@@ -867,6 +875,8 @@ bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int6
                   : default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, rows);
   if (!(cfg && cfg->cache_hints) && c64_ip5 && a.t.hints == kHintStreamStores)
     a.t.hints = kHintStreamWriteThrough;
+  if (!(cfg && cfg->cache_hints) && c64_ip6 && a.t.hints != kHintPlain)
+    a.t.hints = kHintStreamLoads;
   a.stages = stages;
   a.inverse = inverse;
   const size_t vb = (s << b) < 16 ? (s << b) : 16;

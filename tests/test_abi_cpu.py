@@ -161,13 +161,16 @@ def test_plan_query_defaults(L):
     assert p["path"] == br.PATH_TILE and p["tile_bits"] == 5 and p["mid_bits"] == 14
     assert p["work_items"] == (2**14 + 2**7) // 2
     assert p["grid_blocks"] % 8 == 0 and p["grid_blocks"] >= p["work_items"]
-    # built-in plans measured on MI355X: complex64 in place -> b = 6,
-    # grouped order, one item per workgroup, dispatch order
+    # built-in plans measured on MI355X: complex64 in place at 128 MiB -> b = 5,
+    # natural order, write-through stores; elsewhere b = 6, grouped order;
+    # one item per workgroup, dispatch order
     p = br.bitrev_plan_query(24, 8)
-    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
-    assert p["cache_hints"] == br.HINTS_STREAM_STORES
-    assert br.bitrev_plan_query(23, 8)["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
-    assert br.bitrev_plan_query(25, 8)["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
+    assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (5, 1, 1, 2)
+    assert p["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
+    for k in (23, 25):
+        p = br.bitrev_plan_query(k, 8)
+        assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
+        assert p["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
     p = br.bitrev_plan_query(28, 8)
     assert (p["tile_bits"], p["variant"], p["order"], p["xcd_remap"]) == (6, 1, 3, 2)
     assert p["cache_hints"] == br.HINTS_STREAM_WRITE_THROUGH
@@ -233,14 +236,14 @@ def test_rows_plan_class_is_the_launch_footprint(L):
 
 def test_tuning_file(L, tmp_path):
     good = tmp_path / "tune.txt"
-    good.write_text("# comment\n\ninplace 8 24 5 0 2 1 2   # trailing comment\n"
+    good.write_text("# comment\n\ninplace 8 24 4 0 2 1 2   # trailing comment\n"
                     "batched 8 -1 4 4 1 0 0\n")
     br.bitrev_load_tuning(str(good))
     try:
         p = br.bitrev_plan_query(24, 8)
-        assert (p["tile_bits"], p["order"], p["variant"], p["xcd_remap"]) == (5, 2, 1, 2)
+        assert (p["tile_bits"], p["order"], p["variant"], p["xcd_remap"]) == (4, 2, 1, 2)
         assert br.bitrev_plan_query(25, 8)["tile_bits"] == 6  # no entry: default
-        assert br.bitrev_plan_query(24, 8)["cache_hints"] == 3  # 8 fields: default hint
+        assert br.bitrev_plan_query(24, 8)["cache_hints"] == 4  # 8 fields: default hint
         p = br.bitrev_plan_query(0, 8, mode=br.MODE_BATCHED)
         assert p["tile_bits"] == 4 and p["order"] == 1 and p["grid_blocks"] == 4 * 256
         for bad in ("inplace 8 24 6 0 2 0\n", "sideways 8 24 6 0 2 0 0\n",
@@ -253,7 +256,7 @@ def test_tuning_file(L, tmp_path):
             with pytest.raises(br.BitrevError):
                 br.bitrev_load_tuning(str(f))
             # a rejected file leaves the loaded table in place
-            assert br.bitrev_plan_query(24, 8)["tile_bits"] == 5
+            assert br.bitrev_plan_query(24, 8)["tile_bits"] == 4
         with pytest.raises(br.BitrevError):
             br.bitrev_load_tuning(str(tmp_path / "missing.txt"))
         v2 = tmp_path / "tune_v2.txt"
@@ -264,7 +267,7 @@ def test_tuning_file(L, tmp_path):
             (7, 3, 1, 1, 2)
     finally:
         br.bitrev_load_tuning(None)
-    assert br.bitrev_plan_query(24, 8)["tile_bits"] == 6
+    assert br.bitrev_plan_query(24, 8)["tile_bits"] == 5
     assert "tuning" in br.bitrev_tuning_format()
 
 
