@@ -855,7 +855,8 @@ bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int6
   // cache hints of the plain kernel for this size.  Complex64 measured
   // otherwise (alternating rounds at 2^24-2^26): in place at b = 5 the
   // natural order up to 128 MiB (1-5 levels at 2^24 +3.4-3.9%; grouped is
-  // 5-6% ahead at 256-512 MiB) with write-through stores; in place at b = 6
+  // 5-6% ahead at 256-512 MiB), with the write-through stores the hint table
+  // gives it; in place at b = 6
   // streaming loads (best or tied at every size); out of place at b = 6 the
   // grouped order in dispatch order (+1.5% at 2^24)
   const uint64_t footprint = n * s * (uint64_t)rows;
@@ -873,8 +874,6 @@ bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int6
   a.t.hints = (cfg && cfg->cache_hints)
                   ? cfg->cache_hints - 1
                   : default_hints(inplace ? kModeInplace : kModeOutofplace, (int)s, n * s, rows);
-  if (!(cfg && cfg->cache_hints) && c64_ip5 && a.t.hints == kHintStreamStores)
-    a.t.hints = kHintStreamWriteThrough;
   if (!(cfg && cfg->cache_hints) && c64_ip6 && a.t.hints != kHintPlain)
     a.t.hints = kHintStreamLoads;
   a.stages = stages;
