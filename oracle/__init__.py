@@ -120,8 +120,9 @@ class Oracle:
 
     def outofplace_mt(self, a: np.ndarray, elem_size: int | None = None):
         """outofplace with the index range split over the host's OpenMP
-        threads, for timing the CPU baseline on all cores.  Returns
-        (dst, threads used)."""
+        threads: the CPU baseline on all cores, and the expected result of
+        the full-size comparisons of multi-GiB arrays.  Returns (dst, threads
+        used)."""
         s, n = self._elems(a, elem_size)
         k = _log2_exact(n)
         out = np.empty_like(a)

@@ -101,9 +101,10 @@ int oracle_outofplace(const void *src, void *dst, int k, size_t elem_size)
 /* The same out-of-place definition with the index range split over the host
  * threads (OpenMP, static schedule): every i is still visited exactly once and
  * dest[rev(i)] <- src[i] with the bitwise rev above, so the result is
- * oracle_outofplace's.  It exists only to time the CPU baseline on all host
- * cores.  Returns the number of threads used, or -1 for an argument outside
- * the domain. */
+ * oracle_outofplace's.  It times the CPU baseline on all host cores and
+ * computes the expected result of the multi-GiB comparisons, where the
+ * one-thread loop would take minutes.  Returns the number of threads used, or
+ * -1 for an argument outside the domain. */
 int oracle_outofplace_mt(const void *src, void *dst, int k, size_t elem_size)
 {
     const unsigned char *in = (const unsigned char *)src;

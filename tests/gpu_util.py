@@ -40,3 +40,25 @@ def assert_bytes_equal(got: np.ndarray, want: np.ndarray, what: str = "") -> Non
     if not np.array_equal(got, want):
         bad = np.flatnonzero(got != want)
         raise AssertionError("%s: %d bytes differ, first at byte %d" % (what, bad.size, bad[0]))
+
+
+def assert_device_equal(t, want: np.ndarray, what: str = "", chunk: int = 1 << 28) -> None:
+    """Byte-exact comparison of a device tensor with a host array of the same
+    size, copied back a chunk at a time through one pinned host buffer, so a
+    multi-GiB result is compared in full without a second host copy of it."""
+    import torch
+    torch.cuda.synchronize()
+    dev = t.detach().contiguous().view(torch.uint8).reshape(-1)
+    want = np.ascontiguousarray(want).view(np.uint8).reshape(-1)
+    assert dev.numel() == want.size, (what, dev.numel(), want.size)
+    buf = torch.empty(min(chunk, max(1, dev.numel())), dtype=torch.uint8, pin_memory=True)
+    view = buf.numpy()
+    for lo in range(0, dev.numel(), chunk):
+        hi = min(dev.numel(), lo + chunk)
+        buf[:hi - lo].copy_(dev[lo:hi])
+        torch.cuda.synchronize()
+        got = view[:hi - lo]
+        if not np.array_equal(got, want[lo:hi]):
+            bad = np.flatnonzero(got != want[lo:hi])
+            raise AssertionError("%s: %d bytes differ in [%d, %d), first at byte %d"
+                                 % (what, bad.size, lo, hi, lo + bad[0]))

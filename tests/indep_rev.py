@@ -21,6 +21,18 @@ def rev_bytetable(i: int, k: int) -> int:
     return r >> (64 - k)
 
 
+def rev_bytetable_array(idx, k: int):
+    """rev_bytetable on a numpy array of indices (uint64 arithmetic, the same
+    string-built table), for brute force at millions of indices."""
+    import numpy as np
+    table = np.array(BYTE_TABLE, dtype=np.uint64)
+    i = np.asarray(idx, dtype=np.uint64)
+    r = np.zeros_like(i)
+    for byte in range(8):
+        r = (r << np.uint64(8)) | table[(i >> np.uint64(8 * byte)) & np.uint64(0xFF)]
+    return r >> np.uint64(64 - k) if k else np.zeros_like(i)
+
+
 def rev_sequence_xor(k: int) -> list[int]:
     """rev_k(i) for i = 0 .. 2^k - 1 by the inductive XOR method (Methods,
     inductive XOR): i ^ (i+1) is a run of t low ones; reversed within k bits it

@@ -26,7 +26,7 @@ import math
 import numpy as np
 
 from indep_rev import (bitrev_evenodd_chain, evenodd_step, read_golden, rev_bytetable,
-                       rev_sequence_xor)
+                       rev_bytetable_array, rev_sequence_xor)
 
 
 def pin_worked_example(o) -> None:
@@ -163,7 +163,8 @@ def pin_element_sizes(o) -> None:
 
 
 def pin_outofplace_threads(o) -> None:
-    """The multi-threaded out-of-place form (CPU-baseline timing only) gives
+    """The multi-threaded out-of-place form (CPU-baseline timing and the
+    full-size comparisons) gives
     the byte-table permutation, for sizes that split unevenly over threads."""
     rng = np.random.default_rng(16)
     for s in (1, 3, 8, 16):
@@ -176,6 +177,23 @@ def pin_outofplace_threads(o) -> None:
             got, threads = o.outofplace_mt(buf, s)
             assert threads >= 1
             assert np.array_equal(got, want.reshape(-1)), (s, k)
+
+
+def pin_outofplace_threads_large(o) -> None:
+    """The multi-threaded out-of-place form, which the full-size comparisons
+    of the multi-GiB configurations use, gives the byte-table permutation on
+    every index of arrays of millions of elements (each thread's static share
+    then spans many cache lines and pages), for 1-, 4- and 16-byte elements."""
+    rng = np.random.default_rng(17)
+    for k, s in ((22, 1), (21, 4), (20, 16)):
+        n = 1 << k
+        buf = rng.integers(0, 256, size=n * s, dtype=np.uint8)
+        perm = rev_bytetable_array(np.arange(n, dtype=np.uint64), k).astype(np.int64)
+        want = np.empty_like(buf).reshape(n, s)
+        want[perm] = buf.reshape(n, s)
+        got, threads = o.outofplace_mt(buf, s)
+        assert threads >= 1
+        assert np.array_equal(got, want.reshape(-1)), (s, k)
 
 
 def pin_special_values(o) -> None:
@@ -286,6 +304,7 @@ def pin_digit_reversal(o) -> None:
 
 ALL_PINS.append(pin_digit_reversal)
 ALL_PINS.append(pin_outofplace_threads)
+ALL_PINS.append(pin_outofplace_threads_large)
 
 
 def pin_evenodd_split(o) -> None:

@@ -2,19 +2,28 @@
 benchmark times (the library's default plan, plus the tile-width sweep).
 
   uint32 n=2^10                     -> test_gpu_parity.test_c1_uint32_n1024
-  complex64 n=2^24, b in {4,5,6}    -> test_c2_*            (full oracle compare)
-  complex128 n=2^28, float32 2^30   -> test_c3_*            (sampled + properties)
-  4096 uneven complex64 arrays      -> test_c4_*            (sampled + properties)
-  256 x 2^16 float32, autograd      -> test_c5_*            (full + FD)
+  complex64 n=2^24, b in {4,5,6}    -> test_c2_*  (full oracle compare, every plan timed)
+  complex128 n=2^28, float32 2^30   -> test_c3_*  (full oracle compare, chunked)
+  4096 uneven complex64 arrays      -> test_c4_*  (full oracle compare, chunked)
+  256 x 2^16 float32, autograd      -> test_c5_*  (full + FD)
+  more than 2^31 elements           -> test_more_than_2p32_* (full oracle compare)
+
+The multi-GiB results are copied back a chunk at a time and compared byte for
+byte with the oracle's result for the whole array, computed on the host: the
+out-of-place definition with its index range split over the host threads
+(the oracle's multi-threaded form), or the in-place definition applied to
+each array of a batch from a pool of host threads.
 """
+import concurrent.futures as cf
 import math
+import os
 
 import numpy as np
 import pytest
 
 import oracle
 import paper_1708_01873_amd as br
-from gpu_util import assert_bytes_equal, to_host_bytes
+from gpu_util import assert_bytes_equal, assert_device_equal, to_host_bytes
 from paper_1708_01873_amd import workloads
 
 torch = pytest.importorskip("torch")
@@ -40,6 +49,41 @@ def _free_gpu():
 def c2():
     host = workloads.complex64_normal(24, workloads.SEEDS["c2"])
     return host, oracle.outofplace(host)
+
+
+@pytest.fixture(scope="module")
+def c2_dev(c2):
+    return torch.from_numpy(c2[0]).cuda()
+
+
+# every (tile width, order) plan the benchmark times at this size, with each
+# tile kernel variant and both XCD mappings
+@pytest.mark.parametrize("xcd", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("b", [4, 5, 6])
+def test_c2_every_timed_plan(c2, c2_dev, b, order, variant, xcd):
+    _, want = c2
+    cfg = dict(tile_bits=b, order=order, variant=variant, xcd_remap=xcd)
+    what = "c2 b=%d order=%d variant=%d xcd=%d" % (b, order, variant, xcd)
+    x = c2_dev.clone()
+    y = br.bitrev_outofplace(x, **cfg)
+    assert_device_equal(y, want, what + " out of place")
+    br.bitrev_inplace(x, **cfg)
+    assert_device_equal(x, want, what + " in place")
+    del x, y
+
+
+@pytest.mark.parametrize("hints", [1, 2, 3, 4])
+@pytest.mark.parametrize("b", [4, 5, 6])
+def test_c2_cache_hints(c2, c2_dev, b, hints):
+    _, want = c2
+    x = c2_dev.clone()
+    y = br.bitrev_outofplace(x, tile_bits=b, cache_hints=hints)
+    assert_device_equal(y, want, "c2 b=%d hints=%d out of place" % (b, hints))
+    br.bitrev_inplace(x, tile_bits=b, cache_hints=hints)
+    assert_device_equal(x, want, "c2 b=%d hints=%d in place" % (b, hints))
+    del x, y
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2])
@@ -73,20 +117,24 @@ def _sampled_check(x, y, k, seed, count=1 << 16):
     (30, "float32", workloads.SEEDS["c3b"]),
 ])
 def test_c3_large(k, dtype, seed):
+    """4 GiB arrays: out of place, in place, and in place again, each compared
+    in full with the oracle (the input itself after the second application)."""
     tdt = getattr(torch, dtype)
     x = workloads.device_normal(1 << k, seed, tdt)
+    s = x.element_size()
+    host = to_host_bytes(x)
     y = br.bitrev_outofplace(x)
-    _sampled_check(x, y, k, seed)
-    keep = x.clone()
-    br.bitrev_inplace(x)          # in place == out of place, everywhere
-    torch.cuda.synchronize()
-    assert torch.equal(x.view(torch.uint8), y.view(torch.uint8))
+    _sampled_check(x, y, k, seed)       # quick first assertion
+    want, _ = oracle.outofplace_mt(host, elem_size=s)
+    assert_device_equal(y, want, "c3 k=%d out of place" % k)
     del y
     _free_gpu()
-    br.bitrev_inplace(x)          # involution: back to the input
-    torch.cuda.synchronize()
-    assert torch.equal(x.view(torch.uint8), keep.view(torch.uint8))
-    del x, keep
+    br.bitrev_inplace(x)
+    assert_device_equal(x, want, "c3 k=%d in place" % k)
+    del want
+    br.bitrev_inplace(x)
+    assert_device_equal(x, host, "c3 k=%d in place twice" % k)
+    del x
     _free_gpu()
 
 
@@ -104,7 +152,15 @@ def test_c4_batched_full():
     ws = torch.empty(br.bitrev_batched_workspace_size(4096), dtype=torch.uint8, device="cuda")
     br.bitrev_batched(x, off, l2, ws)
     assert br.bitrev_batched_errors(ws) == (0, -1)
-    # sampled against the oracle: 64 positions per array
+    # in full against the oracle: its in-place definition on every array of
+    # a host copy of the input, the arrays spread over a pool of host threads
+    # (each call works on its own array; the calls release the GIL)
+    want = to_host_bytes(keep).view(np.complex64).copy()
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda a: oracle.inplace(want[offsets[a]:offsets[a + 1]]), range(4096)))
+    assert_device_equal(x, want, "c4 batched, all 4096 arrays")
+    del want
+    # sampled against the oracle's rev: 64 positions per array
     rng = np.random.default_rng(seed)
     tables = {}
     src_idx, dst_idx = [], []
@@ -232,24 +288,25 @@ def test_autograd_gradcheck_and_double_backward():
 @pytest.mark.parametrize("k,s", [(32, 1), (31, 2)])
 def test_more_than_2p32_elements_or_bytes(k, s):
     """Element indices beyond 2^31 (k = 31, 32): 64-bit offsets throughout.
-    Sampled against the oracle's rev, then in place == out of place and the
-    involution on the whole array."""
+    Out of place, in place and in place again, each compared in full with the
+    oracle (the input after the second application)."""
     n = 1 << k
     dt = torch.uint8 if s == 1 else torch.int16
     x = torch.empty(n, dtype=dt, device="cuda")
     g = torch.Generator(device="cuda")
     g.manual_seed(k)
     x.view(torch.uint8).random_(0, 256, generator=g)
+    host = to_host_bytes(x)
     y = br.bitrev_outofplace(x)
-    _sampled_check(x, y, k, seed=k)
-    keep = x.clone()
-    br.bitrev_inplace(x)
-    torch.cuda.synchronize()
-    assert torch.equal(x, y)
+    _sampled_check(x, y, k, seed=k)     # quick first assertion
+    want, _ = oracle.outofplace_mt(host, elem_size=s)
+    assert_device_equal(y, want, "k=%d out of place" % k)
     del y
     _free_gpu()
     br.bitrev_inplace(x)
-    torch.cuda.synchronize()
-    assert torch.equal(x, keep)
-    del x, keep
+    assert_device_equal(x, want, "k=%d in place" % k)
+    del want
+    br.bitrev_inplace(x)
+    assert_device_equal(x, host, "k=%d in place twice" % k)
+    del x
     _free_gpu()
