@@ -337,15 +337,24 @@ bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int6
 /* The paper's recursive scheme, as an A/B baseline for the one-pass kernels */
 /* ------------------------------------------------------------------------ */
 
-/* In place, by the paper's cache-oblivious recursive method with one level of
- * recursion (Methods, "cache-oblivious recursive bit-reversed permutation";
- * Results, where the GPU variant uses this scheme): with k = log2n even and
- * h = k/2, (1) reverse the low h bits within each of the 2^h contiguous
- * blocks, (2) transpose the 2^h x 2^h matrix in place, (3) reverse within each
- * block again.  Three passes over the array (3 * 2 n s bytes) where
- * bitrev_inplace makes one; the result is identical.  Odd log2n returns
- * BITREV_ERROR_NOT_SUPPORTED (the paper's odd-k pre-step needs an n/2
- * buffer).  Arguments as bitrev_inplace. */
+/* In place, by the paper's cache-oblivious recursive method (Methods,
+ * "cache-oblivious recursive bit-reversed permutation"; Results, where its
+ * GPU variant recurses twice and needs k divisible by 4): with k = log2n
+ * even and h = k/2, (1) reverse the low h bits within each of the 2^h
+ * contiguous blocks, (2) transpose the 2^h x 2^h matrix in place, (3)
+ * reverse within each block again.  levels = 2: the block reversals of (1)
+ * and (3) recurse once more -- each block is staged in LDS and reversed
+ * there by the same three steps on h/2 bits -- which needs h even and a
+ * block of at most 64 KiB (2^h * elem_size), else BITREV_ERROR_NOT_SUPPORTED.
+ * levels = 1: the block reversals are the one-pass tile kernels.  levels = 0:
+ * two where they apply, else one.  Three passes over the array (3 * 2 n s
+ * bytes) either way, where bitrev_inplace makes one; the result is
+ * identical.  Odd log2n returns BITREV_ERROR_NOT_SUPPORTED (the paper's
+ * odd-k pre-step needs an n/2 buffer).  Other arguments as bitrev_inplace;
+ * levels outside 0..2 returns BITREV_ERROR_INVALID_VALUE. */
+bitrev_status_t bitrev_inplace_recursive_ex(void* data, int log2n, size_t elem_size, int levels,
+                                            void* stream);
+/* bitrev_inplace_recursive_ex with levels = 0. */
 bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size, void* stream);
 
 /* In-place transpose of a square 2^log2side x 2^log2side row-major matrix of
@@ -366,6 +375,23 @@ bitrev_status_t bitrev_transpose_inplace(void* data, int log2side, size_t elem_s
 bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream);
 bitrev_status_t bitrev_copy_ex(const void* src, void* dst, size_t bytes, int cache_hints,
                                void* stream);
+
+/* The reference copy in the tile kernels' order: dst = src for 2^log2n
+ * elements of elem_size bytes, visiting the tiles of the out-of-place plan
+ * (tile width b, tile order, XCD mapping, cache hints and grid from cfg or
+ * the plan's own choice; variant is ignored) and copying each tile's 2^b
+ * rows of 2^b elements to the same place of dst.  It reads exactly what the
+ * out-of-place permutation reads, in the same order and row shape, and
+ * writes rows of the same shape, without the LDS stage: a copy that walks
+ * memory the way the tile kernels do, used with the linear copy to bound the
+ * permutation (on MI355X a linear sweep over multi-GiB arrays is slower than
+ * the tile order).  src and dst must not overlap (BITREV_ERROR_ALIAS) and
+ * must be aligned to elem_size; a base that is not 16-byte aligned (or, for
+ * rows shorter than 16 bytes, aligned to the row) returns
+ * BITREV_ERROR_NOT_SUPPORTED.  Arrays of at most 64 elements are copied
+ * linearly. */
+bitrev_status_t bitrev_copy_tiled(const void* src, void* dst, int log2n, size_t elem_size,
+                                  const bitrev_config_t* cfg, void* stream);
 
 const char* bitrev_status_string(bitrev_status_t status);
 int bitrev_last_hip_error(void);

@@ -93,7 +93,9 @@ _SIGNATURES = {
     "bitrev_digitrev_outofplace_ex": ([_VP, _VP, _I, _I, _SZ, _CFGP, _VP], _I),
     "bitrev_copy": ([_VP, _VP, _SZ, _VP], _I),
     "bitrev_copy_ex": ([_VP, _VP, _SZ, _I, _VP], _I),
+    "bitrev_copy_tiled": ([_VP, _VP, _I, _SZ, _CFGP, _VP], _I),
     "bitrev_inplace_recursive": ([_VP, _I, _SZ, _VP], _I),
+    "bitrev_inplace_recursive_ex": ([_VP, _I, _SZ, _I, _VP], _I),
     "bitrev_dit_stages": ([_VP, _VP, _I, _I64, _I, _I, _I, _VP], _I),
     "bitrev_dit_stages_ex": ([_VP, _VP, _I, _I64, _I, _I, _I, _CFGP, _VP], _I),
     "bitrev_digitrev_inplace": ([_VP, _I, _I, _SZ, _VP], _I),
@@ -445,6 +447,22 @@ def bitrev_copy(src, dst, stream=None, *, cache_hints=0):
     return dst
 
 
+def bitrev_copy_tiled(src, dst, *, tile_bits=0, grid_blocks=0, order=0, xcd_remap=0,
+                      cache_hints=0, config=None, stream=None):
+    """The reference copy in the tile kernels' order (dst = src), visiting
+    the tiles of the out-of-place plan for src's length; plan fields as in
+    Config (0: the plan's own choice)."""
+    sp, s = _tensor_args(src, "src")
+    dp, s2 = _tensor_args(dst, "dst")
+    if s != s2 or src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same element size and length")
+    k = _log2_exact(src.numel())
+    cfg = _config(tile_bits, grid_blocks, order, config, 0, xcd_remap, cache_hints)
+    _check(_load().bitrev_copy_tiled(sp, dp, k, s, None if cfg is None else ctypes.byref(cfg),
+                                     _stream(stream)), "bitrev_copy_tiled")
+    return dst
+
+
 def bitrev_digitrev_inplace(data, digit_bits: int, log2n: Optional[int] = None, *, tile_bits=0,
                             grid_blocks=0, order=0, xcd_remap=0, cache_hints=0, config=None,
                             stream=None):
@@ -512,14 +530,22 @@ def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, 
     return dst
 
 
-def bitrev_inplace_recursive(data, log2n: Optional[int] = None, *, stream=None):
+def bitrev_inplace_recursive(data, log2n: Optional[int] = None, *, levels: int = 0,
+                             stream=None):
     """In place by the paper's recursive scheme (three passes: block-local
     reversals, square transpose, block-local reversals); log2n must be even.
-    An A/B baseline for bitrev_inplace, which makes one pass."""
+    levels: 2 = the block reversals recurse once more in LDS (log2n divisible
+    by 4, blocks of at most 64 KiB), 1 = they are the one-pass tile kernels,
+    0 = two where they apply.  An A/B baseline for bitrev_inplace, which
+    makes one pass."""
     ptr, s = _tensor_args(data, "data")
     k = _log2_exact(data.numel()) if log2n is None else int(log2n)
-    _check(_load().bitrev_inplace_recursive(ptr, k, s, _stream(stream)),
-           "bitrev_inplace_recursive")
+    if levels:
+        _check(_load().bitrev_inplace_recursive_ex(ptr, k, s, int(levels), _stream(stream)),
+               "bitrev_inplace_recursive_ex")
+    else:
+        _check(_load().bitrev_inplace_recursive(ptr, k, s, _stream(stream)),
+               "bitrev_inplace_recursive")
     return data
 
 

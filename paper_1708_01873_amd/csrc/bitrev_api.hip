@@ -890,18 +890,55 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
   return bitrev_dit_stages_ex(src, dst, log2n, rows, stages, inverse, dtype, NULL, stream);
 }
 
-bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size, void* stream) {
+// The block-local reversals with the second recursion level in LDS: 2^h
+// contiguous blocks of 2^h elements each.
+static bitrev_status_t run_block_recursive(void* data, int h, size_t s, hipStream_t st) {
+  DeviceInfo d;
+  bitrev_status_t status = device_info(&d, false);
+  if (status != BITREV_SUCCESS) return status;
+  const uint64_t nblocks = 1ull << h;
+  // two 64 KiB blocks fit a compute unit's LDS at once
+  const uint64_t cap = (uint64_t)d.cus * 8;
+  const uint32_t grid = (uint32_t)(nblocks < cap ? nblocks : cap);
+  const bool vec = reinterpret_cast<uintptr_t>(data) % 16 == 0 && (s << h) % 16 == 0;
+  hipError_t e;
+  switch (s) {
+    case 1: e = launch_block_recursive_s1(data, h, nblocks, vec, grid, st); break;
+    case 2: e = launch_block_recursive_s2(data, h, nblocks, vec, grid, st); break;
+    case 4: e = launch_block_recursive_s4(data, h, nblocks, vec, grid, st); break;
+    case 8: e = launch_block_recursive_s8(data, h, nblocks, vec, grid, st); break;
+    default: e = launch_block_recursive_s16(data, h, nblocks, vec, grid, st); break;
+  }
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+}
+
+// Largest block the LDS stage of the second recursion level holds.
+constexpr size_t kRecursiveBlockBytes = 65536;
+
+bitrev_status_t bitrev_inplace_recursive_ex(void* data, int log2n, size_t elem_size, int levels,
+                                            void* stream) {
   if (data == NULL || log2n < 0 || log2n > BITREV_MAX_LOG2N || !valid_elem_size(elem_size) ||
-      reinterpret_cast<uintptr_t>(data) % elem_size)
+      reinterpret_cast<uintptr_t>(data) % elem_size || levels < 0 || levels > 2)
     return BITREV_ERROR_INVALID_VALUE;
   if (log2n % 2) return BITREV_ERROR_NOT_SUPPORTED;
-  if (log2n <= 1) return BITREV_SUCCESS;
   const int h = log2n / 2;
+  const bool two_fit = h % 2 == 0 && (elem_size << h) <= kRecursiveBlockBytes;
+  if (levels == 2 && !two_fit) return BITREV_ERROR_NOT_SUPPORTED;
+  if (log2n <= 1) return BITREV_SUCCESS;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
   const int64_t rows = (int64_t)1 << h;
-  bitrev_status_t st = run_plain(data, data, h, rows, elem_size, NULL, stream);
-  if (st == BITREV_SUCCESS) st = run_transpose(data, h, elem_size, static_cast<hipStream_t>(stream));
-  if (st == BITREV_SUCCESS) st = run_plain(data, data, h, rows, elem_size, NULL, stream);
+  const bool two = levels == 2 || (levels == 0 && two_fit);
+  bitrev_status_t st = two ? run_block_recursive(data, h, elem_size, hs)
+                           : run_plain(data, data, h, rows, elem_size, NULL, stream);
+  if (st == BITREV_SUCCESS) st = run_transpose(data, h, elem_size, hs);
+  if (st == BITREV_SUCCESS)
+    st = two ? run_block_recursive(data, h, elem_size, hs)
+             : run_plain(data, data, h, rows, elem_size, NULL, stream);
   return st;
+}
+
+bitrev_status_t bitrev_inplace_recursive(void* data, int log2n, size_t elem_size, void* stream) {
+  return bitrev_inplace_recursive_ex(data, log2n, elem_size, 0, stream);
 }
 
 bitrev_status_t bitrev_inplace(void* data, int log2n, size_t elem_size, void* stream) {
@@ -1019,16 +1056,20 @@ size_t bitrev_batched_workspace_size(int64_t num_arrays) {
 
 // Common body of the batched entry points; src != NULL means out of place
 // (src -> data, the same packed layout).
-static bitrev_status_t run_batched(const void* src, void* data, int64_t data_elems,
-                                   const int64_t* offsets, const int32_t* log2n,
-                                   int64_t num_arrays, size_t elem_size, void* workspace,
-                                   size_t workspace_bytes, const bitrev_config_t* cfg,
-                                   void* stream) {
-  // ---- validation: no HIP call before this block completes ----
+// Host-side checks of a batched call's arguments other than the workspace
+// (no HIP call is made).  *nothing_to_do is set for num_arrays == 0.
+static bitrev_status_t check_batched_args(const void* src, void* data, int64_t data_elems,
+                                          const int64_t* offsets, const int32_t* log2n,
+                                          int64_t num_arrays, size_t elem_size,
+                                          const bitrev_config_t* cfg, bool* nothing_to_do) {
+  *nothing_to_do = false;
   if (num_arrays < 0 || num_arrays > (1ll << 40) || data_elems < 0 || !valid_elem_size(elem_size) ||
       !valid_config(cfg))
     return BITREV_ERROR_INVALID_VALUE;
-  if (num_arrays == 0) return BITREV_SUCCESS;
+  if (num_arrays == 0) {
+    *nothing_to_do = true;
+    return BITREV_SUCCESS;
+  }
   if (data == NULL || offsets == NULL || log2n == NULL) return BITREV_ERROR_INVALID_VALUE;
   if (reinterpret_cast<uintptr_t>(data) % elem_size || reinterpret_cast<uintptr_t>(offsets) % 8 ||
       reinterpret_cast<uintptr_t>(log2n) % 4)
@@ -1039,6 +1080,19 @@ static bitrev_status_t run_batched(const void* src, void* data, int64_t data_ele
     const uint64_t bytes = (uint64_t)data_elems * elem_size;
     if (src == data || ranges_overlap(src, bytes, data, bytes)) return BITREV_ERROR_ALIAS;
   }
+  return BITREV_SUCCESS;
+}
+
+static bitrev_status_t run_batched(const void* src, void* data, int64_t data_elems,
+                                   const int64_t* offsets, const int32_t* log2n,
+                                   int64_t num_arrays, size_t elem_size, void* workspace,
+                                   size_t workspace_bytes, const bitrev_config_t* cfg,
+                                   void* stream) {
+  // ---- validation: no HIP call before this block completes ----
+  bool nothing = false;
+  const bitrev_status_t chk = check_batched_args(src, data, data_elems, offsets, log2n, num_arrays,
+                                                 elem_size, cfg, &nothing);
+  if (chk != BITREV_SUCCESS || nothing) return chk;
   if (workspace == NULL || reinterpret_cast<uintptr_t>(workspace) % 8 ||
       workspace_bytes < bitrev_batched_workspace_size(num_arrays))
     return BITREV_ERROR_WORKSPACE;
@@ -1166,6 +1220,52 @@ bitrev_status_t bitrev_copy_ex(const void* src, void* dst, size_t bytes, int cac
 
 bitrev_status_t bitrev_copy(const void* src, void* dst, size_t bytes, void* stream) {
   return bitrev_copy_ex(src, dst, bytes, 0, stream);
+}
+
+bitrev_status_t bitrev_copy_tiled(const void* src, void* dst, int log2n, size_t elem_size,
+                                  const bitrev_config_t* cfg, void* stream) {
+  // ---- validation: no HIP call before this block completes ----
+  if (src == NULL || dst == NULL || log2n < 0 || log2n > BITREV_MAX_LOG2N ||
+      !valid_elem_size(elem_size) || !valid_config(cfg) ||
+      (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % elem_size)
+    return BITREV_ERROR_INVALID_VALUE;
+  const uint64_t bytes = (uint64_t)elem_size << log2n;
+  if (overlap(src, dst, (size_t)bytes)) return BITREV_ERROR_ALIAS;
+  // ---- plan and launch ----
+  DeviceInfo d;
+  bitrev_status_t st = device_info(&d, false);
+  if (st != BITREV_SUCCESS) return st;
+  Plan p;
+  st = plan_plain(kModeOutofplace, log2n, (int)elem_size, 1, cfg, pointer_align(src, dst), d, true,
+                  &p);
+  if (st != BITREV_SUCCESS) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (p.path != BITREV_PATH_TILE) {
+    // arrays of at most 64 elements have no tiles: a plain copy
+    const hipError_t e = launch_copy(src, dst, (size_t)bytes, 1, kHintPlain, hs);
+    return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
+  }
+  if (!p.vec) return BITREV_ERROR_NOT_SUPPORTED;
+  TileLaunch a;
+  a.src = src;
+  a.dst = dst;
+  a.m = p.m;
+  a.items_per_seg = a.total_items = 1ull << p.m;
+  a.seg_elems = a.dst_seg_elems = 1ull << log2n;
+  a.balanced = order_code(p.order);
+  a.xcds = p.xcd_remap == 2 ? 1 : d.xcds;
+  a.grid = (cfg && cfg->grid_blocks > 0) ? p.grid : default_grid(a.total_items, d);
+  a.pipelined = 0;
+  a.hints = p.hints;
+  hipError_t e;
+  switch (elem_size) {
+    case 1: e = launch_tile_copy_s1(p.b, a, hs); break;
+    case 2: e = launch_tile_copy_s2(p.b, a, hs); break;
+    case 4: e = launch_tile_copy_s4(p.b, a, hs); break;
+    case 8: e = launch_tile_copy_s8(p.b, a, hs); break;
+    default: e = launch_tile_copy_s16(p.b, a, hs); break;
+  }
+  return e == hipSuccess ? BITREV_SUCCESS : hip_fail(e);
 }
 
 const char* bitrev_status_string(bitrev_status_t status) {

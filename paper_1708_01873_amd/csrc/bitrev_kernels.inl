@@ -86,6 +86,38 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_outofplace
   }
 }
 
+// A copy in the out-of-place tile kernels' order (the identity map in
+// place of the reversal): work item -> tile y; its 2^b rows of src are
+// written to the same places of dst.  Same reads, same row shape on the
+// write side, no LDS stage: the reference copy for the tile kernels where a
+// linear sweep is not the fastest way through memory.
+template <int S, int B, int H>
+__global__ __launch_bounds__((tile_threads<S, B, true>())) void k_tile_copy(
+    const void* src, void* dst, int m, uint64_t total_items, int balanced, int xcds) {
+  typedef typename Bytes<S>::T E;
+  typedef TileShape<S, B, true> Sh;
+  typedef typename Bytes<Sh::VB>::T V;
+  constexpr int NT = tile_threads<S, B, true>();
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  const uint64_t rowstride = 1ull << (m + B);
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    const uint32_t y = oop_tile_at(m, (uint32_t)item, balanced);
+    Chunk<S, Sh::VB> r[PT];
+    tile_load<S, B, true, NT, PT, H>(r, static_cast<const E*>(src), rowstride, y);
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int q = (int)threadIdx.x + i * NT;
+      if (Sh::CPT % NT == 0 || q < Sh::CPT) {
+        const int x = q / Sh::CPR;
+        const int zc = q % Sh::CPR;
+        const uint64_t off =
+            (uint64_t)x * rowstride + (uint64_t)y * Sh::R + (uint64_t)(zc * Sh::CE);
+        st_hint<H>(reinterpret_cast<V*>(static_cast<E*>(dst) + off), r[i].v);
+      }
+    }
+  }
+}
+
 // Where work item `item` lives: its array's base and its middle bits.
 template <typename E>
 __device__ __forceinline__ E* item_base(void* data, uint64_t item, uint64_t items_per_seg,
@@ -200,6 +232,75 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_transpose_inpla
     uint32_t tr, tc;
     tri_pair(item, &tr, &tc);
     tile_pair_transpose<S, B, VEC, NT>(static_cast<E*>(data), h, tr, tc, lds);
+    __syncthreads();
+  }
+}
+
+// The paper's recursive method one level further down (Methods, recursive
+// permutation; Results: its GPU variant recurses twice), for the
+// block-local reversals of the recursive scheme: each contiguous block of
+// 2^h elements (h even) is staged in LDS and reversed there by the same
+// three steps the whole array goes through -- reverse the low h/2 bits
+// within every run of 2^(h/2) elements, transpose the 2^(h/2) x 2^(h/2)
+// square, reverse the low h/2 bits again.  Each step is an involution, done
+// by swapping the pairs i < f(i) in LDS between barriers.  Dynamic LDS holds
+// one block (2^h * S bytes).
+template <int S, bool VEC>
+__global__ __launch_bounds__(512) void k_block_recursive(void* data, int h, uint64_t nblocks) {
+  typedef typename Bytes<S>::T E;
+  extern __shared__ __align__(16) unsigned char block_lds[];
+  E* lds = reinterpret_cast<E*>(block_lds);
+  const uint32_t n = 1u << h;
+  const int q = h >> 1;
+  const uint32_t low = (1u << q) - 1u;
+  const uint32_t nvec = VEC ? (uint32_t)(((uint64_t)n * S) / 16) : 0u;
+  for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    E* base = static_cast<E*>(data) + blk * (uint64_t)n;
+    if constexpr (VEC) {
+      const u32x4* src = reinterpret_cast<const u32x4*>(base);
+      u32x4* l = reinterpret_cast<u32x4*>(block_lds);
+      for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) l[v] = src[v];
+    } else {
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lds[i] = base[i];
+    }
+    __syncthreads();
+    // step 1: [r | c] -> [r | rev(c)]
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t j = (i & ~low) | rev_bits(i & low, q);
+      if (i < j) {
+        const E t = lds[i];
+        lds[i] = lds[j];
+        lds[j] = t;
+      }
+    }
+    __syncthreads();
+    // step 2: the square transpose, [r | c] -> [c | r]
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t j = ((i & low) << q) | (i >> q);
+      if (i < j) {
+        const E t = lds[i];
+        lds[i] = lds[j];
+        lds[j] = t;
+      }
+    }
+    __syncthreads();
+    // step 3: [r | c] -> [r | rev(c)] again
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t j = (i & ~low) | rev_bits(i & low, q);
+      if (i < j) {
+        const E t = lds[i];
+        lds[i] = lds[j];
+        lds[j] = t;
+      }
+    }
+    __syncthreads();
+    if constexpr (VEC) {
+      u32x4* dst = reinterpret_cast<u32x4*>(base);
+      const u32x4* l = reinterpret_cast<const u32x4*>(block_lds);
+      for (uint32_t v = threadIdx.x; v < nvec; v += blockDim.x) dst[v] = l[v];
+    } else {
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) base[i] = lds[i];
+    }
     __syncthreads();
   }
 }
@@ -613,6 +714,28 @@ hipError_t dispatch_digit(int b, bool vec, const TileLaunch& a, hipStream_t st) 
   }
 }
 
+template <int S, int B, int H>
+hipError_t run_tile_copy(const TileLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_tile_copy<S, B, H>), dim3(a.grid), dim3(tile_threads<S, B, true>()), 0, st,
+                     a.src, a.dst, a.m, a.total_items, a.balanced, a.xcds);
+  return hipGetLastError();
+}
+
+template <int S, int B = 0>
+hipError_t dispatch_tile_copy(int b, const TileLaunch& a, hipStream_t st) {
+  if constexpr (B > max_tile_bits(S)) {
+    return hipErrorInvalidValue;
+  } else {
+    if (b != B) return dispatch_tile_copy<S, B + 1>(b, a, st);
+    switch (a.hints) {
+      case kHintStreamLoads: return run_tile_copy<S, B, kHintStreamLoads>(a, st);
+      case kHintStreamStores: return run_tile_copy<S, B, kHintStreamStores>(a, st);
+      case kHintStreamWriteThrough: return run_tile_copy<S, B, kHintStreamWriteThrough>(a, st);
+      default: return run_tile_copy<S, B, kHintPlain>(a, st);
+    }
+  }
+}
+
 template <int S, int B = kMinBatchedTileBits>
 hipError_t dispatch_batched(const BatchedLaunch& a, hipStream_t st) {
   if constexpr (B > max_tile_bits(S)) {
@@ -673,6 +796,23 @@ hipError_t BITREV_CAT(launch_tile_inplace_s, BITREV_S)(int b, bool vec, const Ti
 hipError_t BITREV_CAT(launch_tile_outofplace_s, BITREV_S)(int b, bool vec, const TileLaunch& a,
                                                           hipStream_t st) {
   return dispatch_tile<BITREV_S>(false, b, vec, a, st);
+}
+
+hipError_t BITREV_CAT(launch_tile_copy_s, BITREV_S)(int b, const TileLaunch& a, hipStream_t st) {
+  return dispatch_tile_copy<BITREV_S>(b, a, st);
+}
+
+hipError_t BITREV_CAT(launch_block_recursive_s, BITREV_S)(void* data, int h, uint64_t nblocks,
+                                                          bool vec, uint32_t grid, hipStream_t st) {
+  const size_t lds = (size_t)BITREV_S << h;
+  if (vec) {
+    hipLaunchKernelGGL((k_block_recursive<BITREV_S, true>), dim3(grid), dim3(512), lds, st, data, h,
+                       nblocks);
+  } else {
+    hipLaunchKernelGGL((k_block_recursive<BITREV_S, false>), dim3(grid), dim3(512), lds, st, data,
+                       h, nblocks);
+  }
+  return hipGetLastError();
 }
 
 hipError_t BITREV_CAT(launch_wave_s, BITREV_S)(const WaveLaunch& a, hipStream_t st) {

@@ -85,6 +85,9 @@ size_t tile_lds_bytes(int s, int b, bool inplace);
                                          hipStream_t st);                            \
   hipError_t launch_wave_s##S(const WaveLaunch& a, hipStream_t st);                  \
   hipError_t launch_batched_s##S(const BatchedLaunch& a, hipStream_t st);            \
+  hipError_t launch_tile_copy_s##S(int b, const TileLaunch& a, hipStream_t st);      \
+  hipError_t launch_block_recursive_s##S(void* data, int h, uint64_t nblocks,        \
+                                         bool vec, uint32_t grid, hipStream_t st);   \
   hipError_t launch_transpose_s##S(int b, bool vec, const TransposeLaunch& a,        \
                                    hipStream_t st);                                  \
   hipError_t launch_digit_s##S(int d, int b, bool vec, const TileLaunch& a,          \

@@ -132,6 +132,30 @@ def test_batched_validation(L):
     assert call(wsb=ws - 1) == br.ERROR_WORKSPACE
 
 
+def test_recursive_levels_validation(L):
+    f = L.bitrev_inplace_recursive_ex
+    assert f(FAKE, 20, 8, 3, None) == br.ERROR_INVALID_VALUE
+    assert f(FAKE, 20, 8, -1, None) == br.ERROR_INVALID_VALUE
+    assert f(None, 20, 8, 0, None) == br.ERROR_INVALID_VALUE
+    assert f(FAKE, 21, 8, 0, None) == br.ERROR_NOT_SUPPORTED      # odd k
+    assert f(FAKE, 22, 8, 2, None) == br.ERROR_NOT_SUPPORTED      # k/2 odd
+    assert f(FAKE, 28, 8, 2, None) == br.ERROR_NOT_SUPPORTED      # 2^14 x 8 B > 64 KiB
+    assert f(FAKE, 0, 8, 2, None) == br.SUCCESS                   # n = 1: nothing to do
+
+
+def test_copy_tiled_validation(L):
+    assert L.bitrev_copy_tiled(None, FAKE, 10, 4, None, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_tiled(FAKE, None, 10, 4, None, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_tiled(FAKE, FAKE + (1 << 16), 10, 3, None, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_tiled(FAKE, FAKE + (1 << 16), 41, 4, None, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_tiled(FAKE, FAKE + (1 << 16), -1, 4, None, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_tiled(FAKE + 2, FAKE + (1 << 16), 10, 4, None, None) == br.ERROR_INVALID_VALUE
+    assert L.bitrev_copy_tiled(FAKE, FAKE + 64, 10, 4, None, None) == br.ERROR_ALIAS
+    cfg = br.Config(0, 0, 4, 0, 0, 0)
+    assert L.bitrev_copy_tiled(FAKE, FAKE + (1 << 16), 10, 4, ctypes.byref(cfg),
+                               None) == br.ERROR_INVALID_VALUE
+
+
 def test_timed_entry_validation(L):
     """The timed entry points need both events (checked before any HIP call)."""
     assert L.bitrev_inplace_timed(FAKE, 20, 8, None, None, FAKE, None) == br.ERROR_INVALID_VALUE
