@@ -105,6 +105,49 @@ def read_traffic(kernel: str):
         return None
 
 
+def kernel_name(inplace: bool, s: int, plan: dict) -> str:
+    """The tile kernel a default plan launches (its template arguments)."""
+    b, hint = plan["tile_bits"], plan["cache_hints"] - 1
+    if inplace:
+        if plan["variant"] == 2:
+            return "k_tile_inplace_pipe<%d,%d,true>" % (s, b)
+        if plan["variant"] == 3:
+            return "k_tile_inplace_rs<%d,%d,true,%d>" % (s, b, hint)
+        return "k_tile_inplace<%d,%d,true,%d>" % (s, b, hint)
+    if plan["variant"] == 2:
+        return "k_tile_outofplace_pipe<%d,%d,true>" % (s, b)
+    return "k_tile_outofplace<%d,%d,true,%d>" % (s, b, hint)
+
+
+def roofline_block(nbytes: float, kms: float, kernel: str, traffic=None) -> dict:
+    """The roofline object of one kernel: algorithmic bytes per launch over
+    its mean duration, against the HBM peak."""
+    return {"bound": "hbm", "achieved": round(gbs(nbytes, kms), 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs(nbytes, kms) / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel": kernel, "algorithmic_bytes_per_launch": nbytes,
+            "kernel_ms_mean": round(kms, 5)}
+
+
+# The paper's reported figures for its own workload (complex<double>, k = 24),
+# on its own hardware (Results; Table 2 gives the CPU's caches and clock).
+# The paper prints seconds; GB/s here is 2 n s / t with s = 16 bytes.
+PAPER_CONTEXT = {
+    "what": "the paper's reported times for the bit-reversed permutation of 2^24 "
+            "complex<double> (16-byte) elements, as context only: other hardware, and "
+            "the GPU figure may include host-device copies",
+    "workload": "complex128 n=2^24 (256 MiB); our figure: "
+                "context.other_configs.complex128_2p24_paper_workload",
+    "fastest_single_thread": {"seconds": 0.13, "GBps_derived": 4.1,
+                              "hardware": "x86-64 CPU, 3.8 GHz, 15360K L3 (model not named), "
+                                          "g++ 6.2.0 -Ofast -march=native"},
+    "semi_recursive_openmp": {"seconds": 0.1, "GBps_derived": 5.4,
+                              "hardware": "the same CPU, thread count not stated"},
+    "semi_recursive_cuda": {"seconds": 0.08, "GBps_derived": 6.7,
+                            "hardware": "an unnamed NVIDIA GPU, nvcc"},
+    "naive_bitwise": {"seconds": 1.0, "GBps_derived": 0.54, "hardware": "the same CPU"},
+}
+
+
 def cpu_model() -> str:
     """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
     try:
@@ -215,6 +258,77 @@ def batched_speedup(torch, br, reps: int):
     }
 
 
+def best_copy(torch, br, timer, x, y, reps: int) -> dict:
+    """The fastest reference copy of x into y under the timer's flush policy:
+    the linear streaming copy in each of its four cache-hint forms and the
+    copy in the out-of-place tile kernels' order (the identity map, same
+    reads and row shape as the permutation) in each form.  Returns the
+    fastest mean step time and which copy gave it."""
+    best = None
+    for tiled in (False, True):
+        for h in (1, 2, 3, 4):
+            if tiled:
+                fn = lambda: br.bitrev_copy_tiled(x, y, cache_hints=h)  # noqa: E731
+            else:
+                fn = lambda: br.bitrev_copy(x, y, cache_hints=h)  # noqa: E731
+            ms = statistics.fmean(timer.time(fn, reps))
+            if best is None or ms < best["ms"]:
+                best = {"ms": ms, "copy": ("tile order" if tiled else "linear"),
+                        "cache_hints": h}
+    return best
+
+
+def kernel_ms(br, timer, fn_timed, reps: int) -> float:
+    """Mean duration of the one kernel a *_timed call launches (HIP events
+    recorded by its own dispatch, system-scope fence off), the caches evicted
+    before each launch."""
+    evs = [(br.TimingEvent(), br.TimingEvent()) for _ in range(reps)]
+    for a, b in evs:
+        timer._flush()
+        fn_timed(a, b)
+    timer.torch.cuda.synchronize()
+    ms = statistics.fmean(a.elapsed_time(b) for a, b in evs)
+    for a, b in evs:
+        a.destroy()
+        b.destroy()
+    return ms
+
+
+def per_n_complex64(torch, br, timer, reps: int) -> dict:
+    """Complex64 in place and out of place at n = 2^22 .. 2^29 (32 MiB to
+    4 GiB), default plans, caches evicted before each call, next to the
+    fastest reference copy of the same bytes.  Arrays up to 128 MiB can be
+    held whole by the 256 MiB Infinity Cache together with what a step
+    writes; from 512 MiB on no step fits it, so those rates are HBM-bound."""
+    from paper_1708_01873_amd import workloads
+    out = {}
+    for k in range(22, 30):
+        n = 1 << k
+        x = workloads.device_normal(n, 100 + k, torch.complex64)
+        y = torch.empty_like(x)
+        nb = 2.0 * n * 8
+        r = reps if k <= 26 else max(4, reps // 2)
+        ip = statistics.fmean(timer.time(lambda: br.bitrev_inplace(x), r))
+        oop = statistics.fmean(timer.time(lambda: br.bitrev_outofplace(x, y), r))
+        ipk = kernel_ms(br, timer, lambda a, b: br.bitrev_inplace_timed(x, a, b), r)
+        cp = best_copy(torch, br, timer, x, y, r)
+        out["2^%d" % k] = {
+            "array_MiB": (n * 8) >> 20,
+            "cache_assisted": n * 8 <= (128 << 20),
+            "inplace_GBps": round(gbs(nb, ip), 1),
+            "inplace_kernel_GBps": round(gbs(nb, ipk), 1),
+            "outofplace_GBps": round(gbs(nb, oop), 1),
+            "copy_GBps": round(gbs(nb, cp["ms"]), 1),
+            "copy_form": "%s, hints %d" % (cp["copy"], cp["cache_hints"]),
+            "inplace_pct_of_copy": round(100.0 * cp["ms"] / ip, 1),
+            "outofplace_pct_of_copy": round(100.0 * cp["ms"] / oop, 1),
+            "inplace_pct_hbm_peak": round(100.0 * gbs(nb, ip) / HBM_PEAK_GBS, 1)}
+        log("per-n complex64 2^%d: %s" % (k, json.dumps(out["2^%d" % k])))
+        del x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def other_configs(torch, br, timer, reps: int) -> dict:
     """The remaining configurations, timed like the headline (default plans,
     caches evicted before each call)."""
@@ -228,20 +342,45 @@ def other_configs(torch, br, timer, reps: int) -> dict:
     out["uint32_2p10"] = {
         "inplace_us": round(1e3 * med(timer.time(lambda: br.bitrev_inplace(x), reps)), 2),
         "outofplace_us": round(1e3 * med(timer.time(lambda: br.bitrev_outofplace(x, y), reps)), 2)}
-    # the two 4 GiB arrays
+    # the two 4 GiB arrays: beyond every cache, so their kernels are the
+    # HBM-bound rooflines (kernel time from each launch's own events)
     for name, k, dt, seed in (("complex128_2p28", 28, torch.complex128, workloads.SEEDS["c3a"]),
                               ("float32_2p30", 30, torch.float32, workloads.SEEDS["c3b"])):
         x = workloads.device_normal(1 << k, seed, dt)
         y = torch.empty_like(x)
-        nb = 2.0 * x.numel() * x.element_size()
-        r = max(2, reps // 4)
+        s = x.element_size()
+        nb = 2.0 * x.numel() * s
+        r = max(4, reps // 4)
+        ip = statistics.fmean(timer.time(lambda: br.bitrev_inplace(x), r))
+        oop = statistics.fmean(timer.time(lambda: br.bitrev_outofplace(x, y), r))
+        ipk = kernel_ms(br, timer, lambda a, b: br.bitrev_inplace_timed(x, a, b), r)
+        oopk = kernel_ms(br, timer, lambda a, b: br.bitrev_outofplace_timed(x, y, a, b), r)
+        cp = best_copy(torch, br, timer, x, y, r)
+        pip = br.bitrev_plan_query(k, s, mode=br.MODE_INPLACE)
+        poop = br.bitrev_plan_query(k, s, mode=br.MODE_OUTOFPLACE)
         out[name] = {
-            "inplace_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_inplace(x), r))), 1),
-            "outofplace_GBps": round(gbs(nb, med(timer.time(lambda: br.bitrev_outofplace(x, y), r))), 1),
-            "copy_GBps": round(gbs(nb, min(med(timer.time(
-                lambda: br.bitrev_copy(x, y, cache_hints=h), r)) for h in (1, 2))), 1)}
+            "inplace_GBps": round(gbs(nb, ip), 1),
+            "outofplace_GBps": round(gbs(nb, oop), 1),
+            "copy_GBps": round(gbs(nb, cp["ms"]), 1),
+            "copy_form": "%s, hints %d" % (cp["copy"], cp["cache_hints"]),
+            "inplace_pct_of_copy": round(100.0 * cp["ms"] / ip, 1),
+            "outofplace_pct_of_copy": round(100.0 * cp["ms"] / oop, 1),
+            "roofline_inplace": roofline_block(nb, ipk, kernel_name(True, s, pip)),
+            "roofline_outofplace": roofline_block(nb, oopk, kernel_name(False, s, poop))}
+        log("%s: %s" % (name, json.dumps(out[name])))
         del x, y
         torch.cuda.empty_cache()
+    # the paper's own workload: complex128 (complex<double>), k = 24
+    x = workloads.device_normal(1 << 24, 24, torch.complex128)
+    y = torch.empty_like(x)
+    nb = 2.0 * x.numel() * 16
+    ip = statistics.fmean(timer.time(lambda: br.bitrev_inplace(x), reps))
+    oop = statistics.fmean(timer.time(lambda: br.bitrev_outofplace(x, y), reps))
+    out["complex128_2p24_paper_workload"] = {
+        "inplace_GBps": round(gbs(nb, ip), 1), "outofplace_GBps": round(gbs(nb, oop), 1),
+        "inplace_ms": round(ip, 5), "inplace_ns_per_element": round(1e6 * ip / (1 << 24), 6)}
+    del x, y
+    torch.cuda.empty_cache()
     # differentiation: 256 x 2^16 float32, forward and backward of BitRev
     xh, wh = workloads.rows_float32(256, 16, workloads.SEEDS["c5"])
     x = torch.from_numpy(xh).cuda().requires_grad_()
@@ -401,12 +540,12 @@ def main() -> int:
 
     # the reference copy of the same bytes under the same flush policy
     y = torch.empty_like(x)
-    # the fastest of the copy's cache-hint forms: the denominator is the best
-    # copy measured, never a slower one
-    copy_ms = min(statistics.fmean(timer.time(lambda: br.bitrev_copy(x, y, cache_hints=h),
-                                              args.steps)) for h in (1, 2, 3, 4))
+    # the fastest copy measured (linear and tile-order copies, each in its
+    # four cache-hint forms): the denominator is never a slower copy
+    copy_best = best_copy(torch, br, timer, x, y, args.steps)
+    copy_ms = copy_best["ms"]
     copy_gbs = gbs(nbytes, copy_ms)
-    log("copy %.1f GB/s (mean %.4f ms)" % (copy_gbs, copy_ms))
+    log("copy %.1f GB/s (mean %.4f ms, %s)" % (copy_gbs, copy_ms, copy_best))
 
     if plan["variant"] == 2:
         kernel = "k_tile_inplace_pipe<8,%d,true>" % plan["tile_bits"]
@@ -438,6 +577,7 @@ def main() -> int:
                    "xcd_remap": plan["xcd_remap"], "cache_hints": plan["cache_hints"]},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "copy_GBps": round(copy_gbs, 2),
+        "copy_form": "%s, hints %d" % (copy_best["copy"], copy_best["cache_hints"]),
         "pct_of_copy": round(100.0 * value / copy_gbs, 2),
         "bit_exact": bit_exact,
         "wall_s_timed_loop": round(wall, 4),
@@ -475,15 +615,25 @@ def main() -> int:
                     "inplace_GBps": round(gbs(nbytes, statistics.fmean(ti)), 2),
                     "outofplace_GBps": round(gbs(nbytes, statistics.fmean(to)), 2)}
         extras["tile_sweep"] = sweep
-        rec = timer.time(lambda: br.bitrev_inplace_recursive(x, k), args.steps)
-        rec_ms = statistics.fmean(rec)
+        rec_ms = statistics.fmean(
+            timer.time(lambda: br.bitrev_inplace_recursive(x, k, levels=2), args.steps))
+        rec1_ms = statistics.fmean(
+            timer.time(lambda: br.bitrev_inplace_recursive(x, k, levels=1), args.steps))
         extras["paper_recursive_scheme"] = {
-            "what": "the paper's recursive method, one recursion level: block-local reversals, "
-                    "in-place square transpose, block-local reversals (3 passes)",
+            "what": "the paper's recursive method as its GPU variant runs it, two recursion "
+                    "levels: block-local reversals of 2^12 elements (each reversed in LDS by "
+                    "the same three steps on 2^6 x 2^6), in-place square transpose, block-local "
+                    "reversals (3 passes over HBM)",
             "GBps_effective": round(gbs(nbytes, rec_ms), 2),
             "ms": round(rec_ms, 5),
-            "slowdown_vs_one_pass": round(rec_ms / mean_ms, 3)}
+            "slowdown_vs_one_pass": round(rec_ms / mean_ms, 3),
+            "one_level": {"what": "one recursion level, the block reversals by the one-pass "
+                                  "tile kernel",
+                          "GBps_effective": round(gbs(nbytes, rec1_ms), 2),
+                          "ms": round(rec1_ms, 5)}}
         extras["other_configs"] = other_configs(torch, br, timer, args.steps)
+        extras["per_n_complex64"] = per_n_complex64(torch, br, timer, max(10, args.steps // 2))
+        extras["paper"] = PAPER_CONTEXT
         hot_timer = Timer(torch, flush=False)
         hot = hot_timer.time(step, args.steps)
         hot_copy = min((hot_timer.time(lambda: br.bitrev_copy(x, y, cache_hints=h), args.steps)
