@@ -48,7 +48,8 @@ typedef enum bitrev_status {
   /* source and destination ranges overlap: use the in-place entry point */
   BITREV_ERROR_ALIAS = 2,
   /* batched workspace missing, misaligned or smaller than
-   * bitrev_batched_workspace_size() */
+   * bitrev_batched_workspace_size(); or more arrays than the built-in
+   * scratch of bitrev_batched_noalloc holds */
   BITREV_ERROR_WORKSPACE = 3,
   /* a HIP runtime call or kernel launch failed; see bitrev_last_hip_error() */
   BITREV_ERROR_HIP = 4,
@@ -207,6 +208,29 @@ bitrev_status_t bitrev_batched_outofplace(const void* src, void* dst, int64_t da
  * workspace wrote.  Either output pointer may be NULL. */
 bitrev_status_t bitrev_batched_errors(const void* workspace, int64_t* num_rejected,
                                       int64_t* first_rejected, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * in-place batched permutation as bitrev_batched with the built-in plan, with
+ * its workspace taken from a fixed array inside the library instead of from
+ * the caller.  No allocating call of any kind is made.
+ *   data, data_elems, offsets, log2n, num_arrays, elem_size, stream: as
+ *   bitrev_batched; the caller still owns data, offsets and log2n.
+ *   num_arrays <= BITREV_NOALLOC_MAX_ARRAYS (65536), else
+ *   BITREV_ERROR_WORKSPACE before any HIP call.
+ * The array (bitrev_batched_workspace_size(BITREV_NOALLOC_MAX_ARRAYS) =
+ * 524,544 bytes, 512 KiB and 256 bytes) exists once
+ * per GPU the library runs on and is held until the process ends.  Every call
+ * on one GPU uses that GPU's array and leaves its contents behind; each call
+ * rewrites all of it that it reads, so nothing has to be cleared between
+ * calls.  Calls that overlap in time on one GPU (other streams, other
+ * threads) race on the array: serialise them.  Rejected arrays are left
+ * untouched as in bitrev_batched, but the rejection count is not readable
+ * (bitrev_batched_errors needs a caller-owned workspace). */
+#define BITREV_NOALLOC_MAX_ARRAYS 65536
+bitrev_status_t bitrev_batched_noalloc(void* data, int64_t data_elems, const int64_t* offsets,
+                                       const int32_t* log2n, int64_t num_arrays, size_t elem_size,
+                                       void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Explicit configuration (autotuner, tile-width sweeps)                     */

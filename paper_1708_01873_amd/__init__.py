@@ -76,6 +76,7 @@ _SIGNATURES = {
     "bitrev_rows": ([_VP, _VP, _I, _I64, _SZ, _VP], _I),
     "bitrev_batched_workspace_size": ([_I64], _SZ),
     "bitrev_batched": ([_VP, _I64, _VP, _VP, _I64, _SZ, _VP, _SZ, _VP], _I),
+    "bitrev_batched_noalloc": ([_VP, _I64, _VP, _VP, _I64, _SZ, _VP], _I),
     "bitrev_batched_errors": ([_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _VP], _I),
     "bitrev_inplace_ex": ([_VP, _I, _SZ, _CFGP, _VP], _I),
     "bitrev_outofplace_ex": ([_VP, _VP, _I, _SZ, _CFGP, _VP], _I),
@@ -363,6 +364,28 @@ def bitrev_batched(data, offsets, log2n, workspace=None, *, tile_bits=0, grid_bl
     else:
         _check(L.bitrev_batched_ex(dp, data.numel(), op, lp, num, s, wp, wbytes,
                                    ctypes.byref(cfg), _stream(stream)), "bitrev_batched_ex")
+    return data
+
+
+NOALLOC_MAX_ARRAYS = 65536  # BITREV_NOALLOC_MAX_ARRAYS
+
+
+def bitrev_batched_noalloc(data, offsets, log2n, *, stream=None):
+    """As bitrev_batched with the built-in plan, for callers that cannot
+    allocate: the workspace is the library's own per-device array (at most
+    NOALLOC_MAX_ARRAYS arrays); nothing is allocated here or in the library.
+    Calls that overlap on one GPU race on that array."""
+    import torch
+    dp, s = _tensor_args(data, "data")
+    if offsets.dtype != torch.int64 or log2n.dtype != torch.int32:
+        raise TypeError("offsets must be int64 and log2n int32")
+    op, _ = _tensor_args(offsets, "offsets")
+    lp, _ = _tensor_args(log2n, "log2n")
+    num = log2n.numel()
+    if offsets.numel() != num + 1:
+        raise ValueError("offsets must have num_arrays + 1 entries")
+    _check(_load().bitrev_batched_noalloc(dp, data.numel(), op, lp, num, s, _stream(stream)),
+           "bitrev_batched_noalloc")
     return data
 
 

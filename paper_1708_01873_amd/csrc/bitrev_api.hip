@@ -1152,6 +1152,63 @@ bitrev_status_t bitrev_batched(void* data, int64_t data_elems, const int64_t* of
                            workspace_bytes, NULL, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free batched call: the workspace lives in a file-scope device
+// array.  Host code never uses the array's name as an address (on the host it
+// is only a stand-in for the symbol); it asks the runtime for the array's
+// device address once per device and passes that to the kernels.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+// bitrev_batched_workspace_size(BITREV_NOALLOC_MAX_ARRAYS) bytes: the
+// header and scan words, rounded up to 256 bytes
+static __device__ __align__(256) int64_t scratch[(BITREV_NOALLOC_MAX_ARRAYS + 3 + 31) / 32 * 32];
+static_assert(sizeof(scratch) == ((size_t)(BITREV_NOALLOC_MAX_ARRAYS + 3) * 8 + 255) / 256 * 256,
+              "scratch must hold the workspace of the largest allowed batch");
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// The current device's address of `scratch`, looked up on the first call on
+// each device with that device current.
+bitrev_status_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= kMaxDevices) return hip_fail(hipErrorInvalidDevice);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BITREV_SUCCESS;
+}
+}  // namespace
+
+extern "C" {
+
+bitrev_status_t bitrev_batched_noalloc(void* data, int64_t data_elems, const int64_t* offsets,
+                                       const int32_t* log2n, int64_t num_arrays, size_t elem_size,
+                                       void* stream) {
+  // every argument, and the size limit, is checked before any HIP call
+  bool nothing = false;
+  const bitrev_status_t chk = check_batched_args(NULL, data, data_elems, offsets, log2n,
+                                                 num_arrays, elem_size, NULL, &nothing);
+  if (chk != BITREV_SUCCESS || nothing) return chk;
+  if (num_arrays > BITREV_NOALLOC_MAX_ARRAYS) return BITREV_ERROR_WORKSPACE;
+  void* ws = nullptr;
+  const bitrev_status_t st = scratch_address(&ws);
+  if (st != BITREV_SUCCESS) return st;
+  // the prep kernel writes every workspace word the persistent kernel reads
+  // (header and scan), so the previous call's contents need no clearing
+  return run_batched(NULL, data, data_elems, offsets, log2n, num_arrays, elem_size, ws,
+                     sizeof(scratch), NULL, stream);
+}
+
 bitrev_status_t bitrev_batched_errors(const void* workspace, int64_t* num_rejected,
                                       int64_t* first_rejected, void* stream) {
   if (workspace == NULL || reinterpret_cast<uintptr_t>(workspace) % 8) return BITREV_ERROR_WORKSPACE;

@@ -156,6 +156,29 @@ def test_copy_tiled_validation(L):
                                None) == br.ERROR_INVALID_VALUE
 
 
+def test_batched_noalloc_validation(L):
+    """The allocation-free batched call checks its arguments, and its array
+    limit, on the host before any HIP call."""
+    lim = br.NOALLOC_MAX_ARRAYS
+    assert lim == 65536
+
+    def call(data=FAKE, elems=1 << 20, off=FAKE, l2=FAKE, num=4096, s=8):
+        return L.bitrev_batched_noalloc(data, elems, off, l2, num, s, None)
+
+    assert call(num=0) == br.SUCCESS
+    assert call(num=lim + 1) == br.ERROR_WORKSPACE
+    assert call(num=1 << 30) == br.ERROR_WORKSPACE
+    assert call(num=-1) == br.ERROR_INVALID_VALUE
+    assert call(data=None) == br.ERROR_INVALID_VALUE
+    assert call(off=None) == br.ERROR_INVALID_VALUE
+    assert call(l2=None) == br.ERROR_INVALID_VALUE
+    assert call(s=12) == br.ERROR_INVALID_VALUE
+    assert call(elems=-1) == br.ERROR_INVALID_VALUE
+    assert call(off=FAKE + 4) == br.ERROR_INVALID_VALUE
+    assert call(l2=FAKE + 2) == br.ERROR_INVALID_VALUE
+    assert call(data=FAKE + 4) == br.ERROR_INVALID_VALUE
+
+
 def test_timed_entry_validation(L):
     """The timed entry points need both events (checked before any HIP call)."""
     assert L.bitrev_inplace_timed(FAKE, 20, 8, None, None, FAKE, None) == br.ERROR_INVALID_VALUE
