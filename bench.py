@@ -148,6 +148,27 @@ PAPER_CONTEXT = {
 }
 
 
+TRAFFIC_ALL_FILE = os.path.join(ROOT, "profiles", "traffic_all_configs.txt")
+
+
+def read_config_traffic(config: str):
+    """HBM bytes per call of one configuration of bench.py --traffic-workload
+    from the committed counter summary, if it was taken on the current
+    kernel source."""
+    try:
+        with open(TRAFFIC_ALL_FILE) as f:
+            text = f.read()
+        if "kernel_source_hash: %s" % kernel_source_hash() not in text:
+            return None
+        for line in text.splitlines():
+            parts = [p.strip() for p in line.split("|")]
+            if len(parts) == 5 and parts[0] == config:
+                return float(parts[2])
+    except (OSError, ValueError):
+        pass
+    return None
+
+
 def cpu_model() -> str:
     """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
     try:
@@ -258,23 +279,35 @@ def batched_speedup(torch, br, reps: int):
     }
 
 
+# Where a shifted copy destination starts inside its allocation: with the
+# destination at the same offset as the source within their allocations, a
+# linear copy's concurrent reads and writes meet the same memory channels;
+# 1 MiB + 8 KiB in, the 4 GiB copy ran up to 5% faster (write-through form).
+COPY_SHIFT_BYTES = (1 << 20) + 8192
+
+
 def best_copy(torch, br, timer, x, y, reps: int) -> dict:
-    """The fastest reference copy of x into y under the timer's flush policy:
-    the linear streaming copy in each of its four cache-hint forms and the
-    copy in the out-of-place tile kernels' order (the identity map, same
-    reads and row shape as the permutation) in each form.  Returns the
-    fastest mean step time and which copy gave it."""
+    """The fastest reference copy of x (the same bytes as the permutation)
+    under the timer's flush policy: the linear streaming copy into y and into
+    a destination shifted by COPY_SHIFT_BYTES, and the copy in the
+    out-of-place tile kernels' order (the identity map, same reads and row
+    shape as the permutation), each in its four cache-hint forms.  Returns
+    the fastest mean step time and which copy gave it."""
+    es = x.element_size()
+    shifted = torch.empty(x.numel() + COPY_SHIFT_BYTES // es, dtype=x.dtype, device=x.device)
+    ys = shifted[COPY_SHIFT_BYTES // es:]
+    forms = []
+    for h in (1, 2, 3, 4):
+        forms.append(("linear", h, lambda h=h: br.bitrev_copy(x, y, cache_hints=h)))
+        forms.append(("linear, shifted destination", h,
+                      lambda h=h: br.bitrev_copy(x, ys, cache_hints=h)))
+        forms.append(("tile order", h, lambda h=h: br.bitrev_copy_tiled(x, y, cache_hints=h)))
     best = None
-    for tiled in (False, True):
-        for h in (1, 2, 3, 4):
-            if tiled:
-                fn = lambda: br.bitrev_copy_tiled(x, y, cache_hints=h)  # noqa: E731
-            else:
-                fn = lambda: br.bitrev_copy(x, y, cache_hints=h)  # noqa: E731
-            ms = statistics.fmean(timer.time(fn, reps))
-            if best is None or ms < best["ms"]:
-                best = {"ms": ms, "copy": ("tile order" if tiled else "linear"),
-                        "cache_hints": h}
+    for name, h, fn in forms:
+        ms = statistics.fmean(timer.time(fn, reps))
+        if best is None or ms < best["ms"]:
+            best = {"ms": ms, "copy": name, "cache_hints": h}
+    del shifted, ys
     return best
 
 
@@ -346,6 +379,7 @@ def other_configs(torch, br, timer, reps: int) -> dict:
     # HBM-bound rooflines (kernel time from each launch's own events)
     for name, k, dt, seed in (("complex128_2p28", 28, torch.complex128, workloads.SEEDS["c3a"]),
                               ("float32_2p30", 30, torch.float32, workloads.SEEDS["c3b"])):
+        label = name.replace("_2p", " 2^")
         x = workloads.device_normal(1 << k, seed, dt)
         y = torch.empty_like(x)
         s = x.element_size()
@@ -365,8 +399,10 @@ def other_configs(torch, br, timer, reps: int) -> dict:
             "copy_form": "%s, hints %d" % (cp["copy"], cp["cache_hints"]),
             "inplace_pct_of_copy": round(100.0 * cp["ms"] / ip, 1),
             "outofplace_pct_of_copy": round(100.0 * cp["ms"] / oop, 1),
-            "roofline_inplace": roofline_block(nb, ipk, kernel_name(True, s, pip)),
-            "roofline_outofplace": roofline_block(nb, oopk, kernel_name(False, s, poop))}
+            "roofline_inplace": roofline_block(nb, ipk, kernel_name(True, s, pip),
+                                               read_config_traffic("in place " + label)),
+            "roofline_outofplace": roofline_block(nb, oopk, kernel_name(False, s, poop),
+                                                  read_config_traffic("out of place " + label))}
         log("%s: %s" % (name, json.dumps(out[name])))
         del x, y
         torch.cuda.empty_cache()
@@ -439,12 +475,15 @@ def traffic_workload(torch, br, workloads) -> None:
     del x, y
     torch.cuda.empty_cache()
     for name, k, dt, seed in (("complex128 2^28", 28, torch.complex128, workloads.SEEDS["c3a"]),
-                              ("float32 2^30", 30, torch.float32, workloads.SEEDS["c3b"])):
+                              ("float32 2^30", 30, torch.float32, workloads.SEEDS["c3b"]),
+                              ("complex64 2^29", 29, torch.complex64, 129)):
         x = workloads.device_normal(1 << k, seed, dt)
         y = torch.empty_like(x)
         nb = 2 * x.numel() * x.element_size()
         run("in place " + name, lambda: br.bitrev_inplace(x), 2, 1, nb)
         run("out of place " + name, lambda: br.bitrev_outofplace(x, y), 2, 1, nb)
+        run("copy, write-through, " + name, lambda: br.bitrev_copy(x, y, cache_hints=4), 2, 1, nb)
+        run("copy in tile order " + name, lambda: br.bitrev_copy_tiled(x, y), 2, 1, nb)
         del x, y
         torch.cuda.empty_cache()
     offsets, log2n = workloads.batched_layout(4096, 8, 20, workloads.SEEDS["c4"])
