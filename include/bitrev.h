@@ -284,16 +284,21 @@ bitrev_status_t bitrev_batched_ex(void* data, int64_t data_elems, const int64_t*
 
 /* The plan a call would use, without launching anything.  mode: 0 in place,
  * 1 out of place, 2 batched (log2n ignored).  Uses the current device's
- * properties when a device is present, else MI355X figures (256 compute
- * units, 160 KiB LDS). */
+ * properties when a device is present, else MI355X figures (gfx950, 256
+ * compute units, 160 KiB LDS). */
 bitrev_status_t bitrev_plan_query(int log2n, size_t elem_size, int64_t rows, int mode,
                                   const bitrev_config_t* cfg, bitrev_plan_t* plan);
 
 /* Load a tuning table (text; see bitrev_tuning_format()).  NULL restores the
- * built-in defaults.  A file that cannot be read or has a malformed line is
- * rejected with BITREV_ERROR_INVALID_VALUE and the table in use is kept.  If
- * the environment variable BITREV_TUNING_FILE names a file, it is loaded at
- * the first call that needs a plan. */
+ * built-in defaults.  Its plan rows have the built-in table's form: each is
+ * keyed by device (gcnArchName, compute units), kind of launch, element size
+ * and size class, so rows tuned on one device or partition mode do not apply
+ * on another; they are consulted before the built-in rows.  Exact entries
+ * keyed by (mode, element size, log2n) override both.  A file that cannot be
+ * read or has a malformed line is rejected with BITREV_ERROR_INVALID_VALUE
+ * and the table in use is kept.  If the environment variable
+ * BITREV_TUNING_FILE names a file, it is loaded at the first call that needs
+ * a plan. */
 bitrev_status_t bitrev_load_tuning(const char* path);
 
 /* One line describing the tuning file's format. */

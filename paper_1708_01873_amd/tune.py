@@ -9,16 +9,22 @@ work-item order, the cache hints of the global accesses and,
 for the batched launch, the workgroups per compute unit matter as well.
 
 ``tune_plain`` and ``tune_batched`` time every candidate with HIP events on
-the launch stream and return the ranking; ``write_tuning`` writes the text
-table ``bitrev_load_tuning`` reads (``bitrev_tuning_format()`` describes it);
-``autotune`` does all three and loads the result.  In-place candidates run an
+the launch stream and return the ranking; ``write_tuning`` writes the best
+plans as plan-table rows keyed by this device (gcnArchName and compute-unit
+count) and by size class, the form ``bitrev_load_tuning`` reads
+(``bitrev_tuning_format()`` describes it); ``autotune`` does all three and
+loads the result.  ``tune_table`` sweeps every element size over a range of
+size classes and writes a whole table in the built-in table's format
+(``csrc/plans_<arch>.inc`` holds the shipped one): rows tuned on one device
+or partition mode do not apply on another.  In-place candidates run an
 even number of times, so the caller's data ends as it started (the
 permutation is an involution).  Tune before capturing a graph: a captured
 launch keeps the plan it was captured with.
 
 Command line: ``python -m paper_1708_01873_amd.tune --out FILE`` tunes the
 in-place and out-of-place plans for a few sizes and the batched plan for an
-uneven complex64 batch, then writes FILE.
+uneven complex64 batch, then writes FILE; ``--table FILE`` sweeps the size
+classes instead and writes a full plan table.
 """
 from __future__ import annotations
 
@@ -35,6 +41,21 @@ from . import (MODE_BATCHED, MODE_INPLACE, MODE_OUTOFPLACE, BitrevError, bitrev_
 
 MAX_TILE_BITS = {1: 7, 2: 7, 4: 7, 8: 6, 16: 6}
 MODE_NAMES = {MODE_INPLACE: "inplace", MODE_OUTOFPLACE: "outofplace", MODE_BATCHED: "batched"}
+ROW_HEADER = ("# arch cus kind elem_size digit_bits tile_match class_min class_max   "
+              "tile_bits wg_per_cu order variant xcd_remap cache_hints")
+
+
+def device_key(device=0) -> tuple[str, int]:
+    """(gcnArchName without its feature suffix, compute units) of a device:
+    the key of the plan-table rows tuned on it."""
+    props = torch.cuda.get_device_properties(device)
+    arch = getattr(props, "gcnArchName", "") or props.name
+    return arch.split(":")[0], props.multi_processor_count
+
+
+def size_class(nbytes: int) -> int:
+    """floor(log2(bytes)): the size class a launch of nbytes is planned by."""
+    return int(nbytes).bit_length() - 1
 _DTYPES = {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64, 16: torch.complex128}
 
 
@@ -48,10 +69,11 @@ class Candidate:
     cache_hints: int = 0
     ms: float = float("inf")
 
-    def line(self, mode: int, elem_size: int, log2n: int) -> str:
-        return "%s %d %d %d %d %d %d %d %d" % (MODE_NAMES[mode], elem_size, log2n, self.tile_bits,
-                                               self.wg_per_cu, self.order, self.variant,
-                                               self.xcd_remap, self.cache_hints)
+    def row(self, arch: str, cus: int, kind: str, elem_size: int, cmin: int, cmax: int) -> str:
+        """This plan as a plan-table row for one device and size-class range."""
+        return "%s %d %s %d 0 0 %d %d   %d %d %d %d %d %d" % (
+            arch, cus, kind, elem_size, cmin, cmax, self.tile_bits, self.wg_per_cu, self.order,
+            self.variant, self.xcd_remap, self.cache_hints)
 
     def config(self) -> dict:
         return dict(tile_bits=self.tile_bits, order=self.order, variant=self.variant,
@@ -66,6 +88,7 @@ class TuneResult:
     best: Candidate
     ranking: list = field(default_factory=list)
     default_ms: float = float("nan")
+    rows: int = 1
 
     @property
     def gain_over_default(self) -> float:
@@ -157,7 +180,7 @@ def tune_plain(log2n: int, elem_size: int, mode: int = MODE_INPLACE, *, rows: in
         raise RuntimeError("no candidate plan ran for log2n=%d elem_size=%d" % (log2n, elem_size))
     ranking.sort(key=lambda c: c.ms)
     default_ms = clock.median_ms(lambda: run(), reps)
-    return TuneResult(mode, elem_size, log2n, ranking[0], ranking, default_ms)
+    return TuneResult(mode, elem_size, log2n, ranking[0], ranking, default_ms, rows)
 
 
 def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 1, 2, 4, 8),
@@ -194,16 +217,25 @@ def tune_batched(data, offsets, log2n, *, reps: int = 6, wg_per_cu=(0, 1, 2, 4, 
     return TuneResult(MODE_BATCHED, s, -1, ranking[0], ranking, default_ms)
 
 
+def result_row(r: TuneResult, arch: str, cus: int) -> str:
+    """The best plan of a result as a plan-table row: keyed by the device, the
+    kind of launch and the size class it was measured at (any class for the
+    batched launch)."""
+    if r.mode == MODE_BATCHED:
+        return r.best.row(arch, cus, "batched", r.elem_size, -1, -1)
+    c = size_class((r.elem_size << r.log2n) * r.rows)
+    return r.best.row(arch, cus, MODE_NAMES[r.mode], r.elem_size, c, c)
+
+
 def write_tuning(results: list[TuneResult], path: str, note: str = "") -> str:
-    """Write the best plan of each result as a libbitrev tuning table."""
+    """Write the best plan of each result as plan-table rows for this device."""
+    arch, cus = device_key()
     props = torch.cuda.get_device_properties(0)
-    lines = ["# libbitrev tuning table (mode elem_size log2n tile_bits wg_per_cu order variant "
-             "xcd_remap cache_hints)",
-             "# device: %s, %d compute units%s" % (props.name, props.multi_processor_count,
-                                                   ("; " + note) if note else "")]
+    lines = ["# libbitrev plan rows tuned on %s (%s, %d compute units)%s"
+             % (props.name, arch, cus, ("; " + note) if note else ""), ROW_HEADER]
     for r in results:
         lines.append("%s   # %.4f ms, %.3fx the built-in plan" % (
-            r.best.line(r.mode, r.elem_size, r.log2n), r.best.ms, r.gain_over_default))
+            result_row(r, arch, cus), r.best.ms, r.gain_over_default))
     d = os.path.dirname(os.path.abspath(path))
     os.makedirs(d, exist_ok=True)
     with open(path, "w") as f:
@@ -224,6 +256,43 @@ def autotune(path: str, plain=((MODE_INPLACE, 8, 24), (MODE_OUTOFPLACE, 8, 24)),
     return results
 
 
+def tune_table(path: str, elem_sizes=(1, 2, 4, 8, 16), classes=range(22, 33), reps: int = 6,
+               note: str = "") -> list[TuneResult]:
+    """Sweep in-place and out-of-place plans for every element size over the
+    size classes (arrays of 2^c bytes, as far as device memory allows) and
+    write one plan-table row per (kind, element size, run of neighbouring
+    classes with the same best plan) for this device, in the built-in
+    table's row format."""
+    arch, cus = device_key()
+    free, _ = torch.cuda.mem_get_info()
+    lines = ["# libbitrev plan table tuned on %s (%d compute units)%s"
+             % (arch, cus, ("; " + note) if note else ""), ROW_HEADER]
+    results = []
+    for mode in (MODE_INPLACE, MODE_OUTOFPLACE):
+        for s in elem_sizes:
+            runs = []  # [plan, first class, last class, candidate]
+            for c in classes:
+                k = c - (s.bit_length() - 1)
+                need = (1 << c) * (1 if mode == MODE_INPLACE else 2) + (1 << 30)
+                if k < 14 or need > free:
+                    continue
+                r = tune_plain(k, s, mode, reps=reps)
+                results.append(r)
+                b = r.best
+                key = (b.tile_bits, b.wg_per_cu, b.order, b.variant, b.xcd_remap, b.cache_hints)
+                if runs and runs[-1][0] == key and runs[-1][2] == c - 1:
+                    runs[-1][2] = c
+                else:
+                    runs.append([key, c, c, b])
+            for _, lo, hi, b in runs:
+                lines.append(b.row(arch, cus, MODE_NAMES[mode], s, lo, hi))
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return results
+
+
 def default_cache_path() -> str:
     props = torch.cuda.get_device_properties(0)
     arch = getattr(props, "gcnArchName", "gpu").split(":")[0]
@@ -239,7 +308,14 @@ def main() -> None:
                     help="comma-separated elem_size:log2n pairs for the plain plans")
     ap.add_argument("--batch", action="store_true",
                     help="also tune the batched plan on 4096 uneven complex64 arrays")
+    ap.add_argument("--table", default=None,
+                    help="sweep every element size over the size classes 2^22 .. 2^32 bytes and "
+                         "write a full plan table (the built-in table's row format) to this file")
     args = ap.parse_args()
+    if args.table:
+        results = tune_table(args.table, reps=args.reps)
+        print("tuned %d (kind, element size, class) plans; wrote %s" % (len(results), args.table))
+        return
     from . import workloads
     plain = []
     for tok in args.sizes.split(","):

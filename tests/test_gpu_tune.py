@@ -60,3 +60,33 @@ def test_tune_batched_keeps_data(tmp_path):
         assert_bytes_equal(to_host_bytes(x), want, "tuned batched plan")
     finally:
         br.bitrev_load_tuning(None)
+
+
+def test_tune_table_rows_load_and_drive_the_plan(tmp_path):
+    """A table swept on this device (two size classes, complex64) is written
+    in the built-in table's row format, keyed by this device; loaded, it
+    drives the plans of those classes, and the plans still compute the
+    permutation."""
+    from paper_1708_01873_amd import tune
+    path = str(tmp_path / "table.txt")
+    results = tune.tune_table(path, elem_sizes=(8,), classes=range(21, 23), reps=2)
+    assert len(results) == 4
+    arch, cus = tune.device_key()
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert rows and all(r[0] == arch and int(r[1]) == cus and len(r) == 14 for r in rows)
+    br.bitrev_load_tuning(path)
+    try:
+        for r in results:
+            p = br.bitrev_plan_query(r.log2n, 8, mode=r.mode)
+            assert (p["tile_bits"], p["order"], p["variant"]) == (
+                r.best.tile_bits, r.best.order, r.best.variant), (r.mode, r.log2n)
+            host = workloads.complex64_normal(r.log2n, 4)
+            x = torch.from_numpy(host).cuda()
+            if r.mode == br.MODE_INPLACE:
+                br.bitrev_inplace(x)
+                got = x
+            else:
+                got = br.bitrev_outofplace(x)
+            assert_bytes_equal(to_host_bytes(got), oracle.outofplace(host), "table plan")
+    finally:
+        br.bitrev_load_tuning(None)
