@@ -356,8 +356,16 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
                                   int inverse, int dtype, void* stream);
 /* The same with a launch configuration: tile_bits (>= stages; the default
  * is the plain kernel's width, at least stages), order, grid_blocks,
- * xcd_remap and cache_hints as in bitrev_config_t; variant is ignored (one
- * work item per workgroup). */
+ * xcd_remap and cache_hints as in bitrev_config_t.  variant: 0 = choose,
+ * 1 = square tiles of 2^b x 2^b, 2 and 3 = out of place only, rectangular
+ * tiles: the index split as [high b | middle | low b - 1] (variant 2) or
+ * [high b | middle | low b - 2] (variant 3), so a tile is 2^b source rows
+ * of 2^(b-1) or 2^(b-2) elements landing as destination rows of 2^b
+ * outputs, the levels' blocks, with a half or a quarter of the square
+ * tile's LDS and threads; b = 5 or 6 and 16-byte aligned arrays, else
+ * BITREV_ERROR_NOT_SUPPORTED.  stages = 0 runs bitrev_rows_ex with this
+ * config, its variant ignored (and a tile width too wide for square tiles
+ * left to the plan). */
 bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int64_t rows,
                                      int stages, int inverse, int dtype,
                                      const bitrev_config_t* cfg, void* stream);

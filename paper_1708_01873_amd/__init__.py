@@ -528,11 +528,12 @@ def bitrev_digitrev_outofplace(src, dst=None, digit_bits: int = 2, log2n: Option
 
 
 def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, log2n=None,
-                      tile_bits=0, grid_blocks=0, order=0, xcd_remap=0, cache_hints=0,
+                      tile_bits=0, grid_blocks=0, order=0, variant=0, xcd_remap=0, cache_hints=0,
                       config=None, stream=None):
     """Bit reversal of each row (last dimension, complex64 or complex128)
     followed by the first `stages` radix-2 DIT FFT levels; ``dst is src``
-    works in place.  Allocates ``dst`` when not given."""
+    works in place.  Allocates ``dst`` when not given.  variant: 1 square
+    tiles, 2 / 3 rectangular tiles out of place (see the C header)."""
     import torch
     if src.dtype not in (torch.complex64, torch.complex128):
         raise TypeError("bitrev_dit_stages needs complex64 or complex128 data")
@@ -547,7 +548,7 @@ def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, 
     if rows << k != src.numel():
         raise ValueError("not a whole number of rows")
     dtype = 0 if src.dtype == torch.complex64 else 1
-    cfg = _config(tile_bits, grid_blocks, order, config, 0, xcd_remap, cache_hints)
+    cfg = _config(tile_bits, grid_blocks, order, config, variant, xcd_remap, cache_hints)
     _check(_load().bitrev_dit_stages_ex(sp, dp, k, rows, int(stages), 1 if inverse else 0, dtype,
                                         cfg, _stream(stream)), "bitrev_dit_stages")
     return dst

@@ -787,7 +787,8 @@ __device__ __forceinline__ void make_twiddles(typename ComplexOf<S>::T* tw) {
 }
 
 // Levels 1 .. stages of the radix-2 DIT butterflies on `rows` staged rows
-// (2^b or 2^(b+1)): for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b),
+// of 2^b elements (a power of two: 2^b or 2^(b+1) for square tiles, fewer
+// for rectangular ones): for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b),
 // w = exp(-+ 2 pi i / 2^s) (sign + for the inverse).  Up to three levels run
 // in one pass over LDS: levels s, s+1, s+2 as a radix-8 step on the eight
 // elements t + j h (j < 8, h = 2^(s-1)) of a block of 2^(s+2), then a radix-4
@@ -826,7 +827,7 @@ __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, in
   constexpr int PE = TileShape<S, B, true>::PE;
   F* base = reinterpret_cast<F*>(lds);
   const F sg = inverse ? (F)-1 : (F)1;  // conjugates the forward twiddles
-  const int rsh = rows > R ? B + 1 : B;  // rows is 2^b or 2^(b+1)
+  const int rsh = 31 - __builtin_clz((unsigned)rows);  // rows is a power of two
   int s = 1;
   while (s <= stages) {
     const int h = 1 << (s - 1);

@@ -363,6 +363,85 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
   }
 }
 
+// Threads of the rectangular-tile DIT kernel: two 16-byte accesses per
+// thread per tile of 2^(BX+BZ) elements, between 64 and 1024.
+template <int S, int BX, int BZ> constexpr int rect_threads() {
+  constexpr int c = ((1 << (BX + BZ)) * S / 16) / 2;
+  return c < 64 ? 64 : (c > 1024 ? 1024 : c);
+}
+
+// Out of place with rectangular tiles, for the fused DIT levels: the index
+// is split as [x (BX bits) | y | z (BZ bits)] with BZ < BX, so rev(i) =
+// [rev z | rev y | rev x].  Source tile y is 2^BX rows of 2^BZ contiguous
+// elements (at a stride of 2^(m+BZ)); it lands on tile rev_m(y) of the
+// destination as 2^BZ rows of 2^BX contiguous outputs (row rev(z), column
+// rev(x), at a stride of 2^(m+BX)).  The levels need destination rows of at
+// least 2^L outputs, which square tiles give only at 2^L rows as well; with
+// BZ < BX a workgroup stages 2^(BX-BZ) times less, so more workgroups share
+// a compute unit and their loads overlap each other's butterfly passes.
+template <int S, int BX, int BZ, int H>
+__global__ __launch_bounds__((rect_threads<S, BX, BZ>())) void k_tile_dit_rect(
+    const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
+    uint64_t seg_elems, int stages, int inverse, int order, int xcds) {
+  typedef typename Bytes<S>::T E;
+  typedef typename ComplexOf<S>::T F;
+  typedef typename Bytes<16>::T V;
+  constexpr int RX = 1 << BX, RZ = 1 << BZ;
+  constexpr int CE = 16 / S;              // elements per 16-byte access
+  constexpr int SRC_CPR = RZ / CE;        // accesses per source row
+  constexpr int DST_CPR = RX / CE;        // accesses per destination row
+  constexpr int CPT = RX * SRC_CPR;       // accesses per tile (either side)
+  constexpr int NT = rect_threads<S, BX, BZ>();
+  constexpr int PT = CPT / NT;
+  constexpr int PE = TileShape<S, BX, true>::PE;  // padded LDS row pitch
+  static_assert(SRC_CPR >= 1 && CPT % NT == 0, "rectangular tile shape");
+  __shared__ E lds[RZ * PE];
+  __shared__ F tw[RX];
+  make_twiddles<S, BX, NT>(tw);
+  const uint64_t src_stride = 1ull << (m + BZ);
+  const uint64_t dst_stride = 1ull << (m + BX);
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    uint64_t seg = 0, local = item;
+    if (items_per_seg != total_items) {
+      seg = item / items_per_seg;
+      local = item - seg * items_per_seg;
+    }
+    const E* in = static_cast<const E*>(src) + seg * seg_elems;
+    E* out = static_cast<E*>(dst) + seg * seg_elems;
+    const uint32_t y = oop_tile_at(m, (uint32_t)local, order);
+    Chunk<S, 16> reg[PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int q = (int)threadIdx.x + i * NT;
+      const uint32_t x = (uint32_t)(q / SRC_CPR), zc = (uint32_t)(q % SRC_CPR);
+      reg[i].v = ld_hint<H>(reinterpret_cast<const V*>(
+          in + (uint64_t)x * src_stride + (uint64_t)y * RZ + zc * CE));
+    }
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int q = (int)threadIdx.x + i * NT;
+      const uint32_t x = (uint32_t)(q / SRC_CPR), zc = (uint32_t)(q % SRC_CPR);
+      const uint32_t col = rev_c<BX>(x);
+#pragma unroll
+      for (int j = 0; j < CE; ++j) lds[rev_c<BZ>(zc * CE + j) * PE + col] = reg[i].e[j];
+    }
+    __syncthreads();
+    dit_rows<S, BX, NT, dit_max_radix<S, BX, false>()>(lds, RZ, stages, inverse != 0, tw);
+    const uint32_t yr = rev_bits(y, m);
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int q = (int)threadIdx.x + i * NT;
+      const uint32_t r = (uint32_t)(q / DST_CPR), cc = (uint32_t)(q % DST_CPR);
+      Chunk<S, 16> c;
+#pragma unroll
+      for (int j = 0; j < CE; ++j) c.e[j] = lds[r * PE + cc * CE + j];
+      st_hint<H>(reinterpret_cast<V*>(out + (uint64_t)r * dst_stride + (uint64_t)yr * RX + cc * CE),
+                 c.v);
+    }
+    __syncthreads();
+  }
+}
+
 template <int S, int B, bool VEC, int H>
 hipError_t run_dit_h(const DitLaunch& a, hipStream_t st) {
   if (a.t.src == a.t.dst) {
@@ -387,6 +466,36 @@ hipError_t run_dit(const DitLaunch& a, hipStream_t st) {
   if (h == kHintStreamStores) return run_dit_h<S, B, VEC, kHintStreamStores>(a, st);
   if (h == kHintStreamWriteThrough) return run_dit_h<S, B, VEC, kHintStreamWriteThrough>(a, st);
   return run_dit_h<S, B, VEC, kHintPlain>(a, st);
+}
+
+template <int S, int BX, int BZ, int H>
+hipError_t run_dit_rect_h(const DitLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_tile_dit_rect<S, BX, BZ, H>), dim3(a.t.grid),
+                     dim3(rect_threads<S, BX, BZ>()), 0, st, a.t.src, a.t.dst, a.t.m,
+                     a.t.items_per_seg, a.t.total_items, a.t.seg_elems, a.stages, a.inverse,
+                     a.t.balanced, a.t.xcds);
+  return hipGetLastError();
+}
+
+template <int S, int BX, int BZ>
+hipError_t run_dit_rect(const DitLaunch& a, hipStream_t st) {
+  switch (a.t.hints) {
+    case kHintStreamLoads: return run_dit_rect_h<S, BX, BZ, kHintStreamLoads>(a, st);
+    case kHintStreamStores: return run_dit_rect_h<S, BX, BZ, kHintStreamStores>(a, st);
+    case kHintStreamWriteThrough: return run_dit_rect_h<S, BX, BZ, kHintStreamWriteThrough>(a, st);
+    default: return run_dit_rect_h<S, BX, BZ, kHintPlain>(a, st);
+  }
+}
+
+// Rectangular tiles: 2^bx source rows of 2^bz elements, bx in {5, 6},
+// bz = bx - 1 or bx - 2 (16-byte aligned arrays only).
+template <int S>
+hipError_t dispatch_dit_rect(int bx, int bz, const DitLaunch& a, hipStream_t st) {
+  if (bx == 6 && bz == 5) return run_dit_rect<S, 6, 5>(a, st);
+  if (bx == 6 && bz == 4) return run_dit_rect<S, 6, 4>(a, st);
+  if (bx == 5 && bz == 4) return run_dit_rect<S, 5, 4>(a, st);
+  if (bx == 5 && bz == 3) return run_dit_rect<S, 5, 3>(a, st);
+  return hipErrorInvalidValue;
 }
 
 template <int S, int B = 1>
@@ -828,6 +937,7 @@ hipError_t BITREV_CAT(launch_transpose_s, BITREV_S)(int b, bool vec, const Trans
 
 #if BITREV_S == 8 || BITREV_S == 16
 hipError_t BITREV_CAT(launch_dit_s, BITREV_S)(int b, bool vec, const DitLaunch& a, hipStream_t st) {
+  if (a.rect_bz > 0) return vec ? dispatch_dit_rect<BITREV_S>(b, a.rect_bz, a, st) : hipErrorInvalidValue;
   return dispatch_dit<BITREV_S>(b, vec, a, st);
 }
 #endif

@@ -47,6 +47,8 @@ struct DitLaunch {
   TileLaunch t;             // the tile geometry (src == dst: in place)
   int stages;               // DIT levels fused after the reversal, <= b
   int inverse;              // 1: exp(+2 pi i ...) twiddles
+  int rect_bz = 0;          // > 0: out of place with rectangular tiles of
+                            // 2^b source rows of 2^rect_bz elements
 };
 
 struct TransposeLaunch {

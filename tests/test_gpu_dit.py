@@ -88,6 +88,48 @@ def test_dit_cache_hints(dtype):
             _check(to_host_bytes(t).view(dtype), x, L, False, dtype)
 
 
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+@pytest.mark.parametrize("b,variant", [(5, 2), (5, 3), (6, 2), (6, 3)])
+def test_dit_rectangular_tiles(dtype, b, variant):
+    """Out of place with rectangular tiles (2^b source rows of 2^(b-1) or
+    2^(b-2) elements): every level count up to b, odd and even array
+    sizes, several rows, every cache hint, both directions."""
+    for k, rows in ((2 * b - variant + 1, 1), (13, 3), (16, 1), (19, 2)):
+        for L in range(0, min(b, k // 2) + 1):   # 2 L <= log2 n, as for square tiles
+            x = _data(k, rows, dtype, 7000 + 100 * k + 10 * L + variant)
+            t = torch.from_numpy(x).cuda().view(rows, 1 << k)
+            inverse = (L + k) % 2 == 1
+            hints = 1 + (L + k + variant) % 4
+            y = br.bitrev_dit_stages(t, stages=L, inverse=inverse, tile_bits=b, variant=variant,
+                                     cache_hints=hints)
+            got = to_host_bytes(y).view(dtype).reshape(rows, -1)
+            for r in range(rows):
+                _check(got[r], x.reshape(rows, -1)[r], L, inverse, dtype)
+
+
+def test_dit_rectangular_tiles_full_size():
+    """The complex64 2^24 array at six fused levels on 2^6 x 2^4 tiles."""
+    x = workloads.complex64_normal(24, workloads.SEEDS["c2"])
+    t = torch.from_numpy(x).cuda()
+    y = br.bitrev_dit_stages(t, stages=6, tile_bits=6, variant=3)
+    _check(to_host_bytes(y).view(np.complex64), x, 6, False, np.complex64)
+
+
+def test_dit_rectangular_tiles_rejected_where_they_do_not_apply():
+    t = torch.zeros(1 << 16, dtype=torch.complex64, device="cuda")
+    for kw in (dict(tile_bits=6, variant=2),):
+        with pytest.raises(br.BitrevError) as e:      # in place
+            br.bitrev_dit_stages(t, t, stages=4, **kw)
+        assert e.value.status == br.ERROR_NOT_SUPPORTED
+    with pytest.raises(br.BitrevError) as e:          # b = 4
+        br.bitrev_dit_stages(t, stages=4, tile_bits=4, variant=2)
+    assert e.value.status == br.ERROR_NOT_SUPPORTED
+    base = torch.zeros((1 << 16) + 1, dtype=torch.complex64, device="cuda")
+    with pytest.raises(br.BitrevError) as e:          # 8-byte aligned only
+        br.bitrev_dit_stages(base[1:], stages=4, tile_bits=5, variant=2)
+    assert e.value.status == br.ERROR_NOT_SUPPORTED
+
+
 def test_dit_rows_and_full_size():
     """Many rows, and the complex64 2^24 array at six fused levels."""
     x = _data(12, 9, np.complex64, 3).reshape(9, 1 << 12)
