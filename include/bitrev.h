@@ -363,7 +363,11 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
  * of 2^(b-1) or 2^(b-2) elements landing as destination rows of 2^b
  * outputs, the levels' blocks, with a half or a quarter of the square
  * tile's LDS and threads; b = 5 or 6 and 16-byte aligned arrays, else
- * BITREV_ERROR_NOT_SUPPORTED.  stages = 0 runs bitrev_rows_ex with this
+ * BITREV_ERROR_NOT_SUPPORTED.  In place (square tiles only: a rectangular
+ * tile's image is not a tile of the same shape) variant 3 keeps the tile
+ * pair in registers and stages its tiles through one LDS tile in turn, with
+ * half the threads (complex64 only, else BITREV_ERROR_NOT_SUPPORTED);
+ * variant 2 in place returns BITREV_ERROR_NOT_SUPPORTED.  stages = 0 runs bitrev_rows_ex with this
  * config, its variant ignored (and a tile width too wide for square tiles
  * left to the plan). */
 bitrev_status_t bitrev_dit_stages_ex(const void* src, void* dst, int log2n, int64_t rows,

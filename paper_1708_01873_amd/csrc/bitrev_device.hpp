@@ -481,19 +481,20 @@ __device__ __forceinline__ void tile_gather(Chunk<S, TileShape<S, B, VEC>::VB> (
 // ---------------------------------------------------------------------------
 // Swizzled LDS stage of the bit-reversal tile kernels for 8-byte elements
 // moved as 16-byte vectors.  An LDS row is 2^L 16-byte slots (L = b - 1) with
-// no padding, and logical slot c of row r is stored at slot c ^ swz(r),
-// swz(r) = rev_L(r mod 2^L).
+// no padding, and logical slot c of row r is stored at slot c ^ swz_key(r).
 //
 // A thread holds chunk q and chunk q + CPT/2, i.e. source rows x and
 // x + R/2 at the same chunk index zc, whose destination columns rev_b(x) and
 // rev_b(x) + 1 are adjacent: each scatter write is one 16-byte slot, half the
 // LDS writes of the element-wise scatter.  The lanes of a wavefront hold
 // consecutive zc of one source row, bound for destination rows
-// r = rev_b(2 zc + j); the low L bits of such an r are rev_L(zc), so
-// swz(r) = zc and the lanes write distinct slots.  The row-order reads (2^L
-// lanes per row, XORed by one constant) are distinct slots too.  Neither
-// side has bank conflicts, where the padded layout's element-wise scatter lost
-// half its LDS cycles to them.  The tiles sit at the same offsets as in the
+// r = rev_b(2 zc + j); the low L bits of such an r are rev_L(zc), and the key
+// spreads their slots over distinct banks (with the bit-reversal key,
+// swz_key(r) = zc).  The row-order reads (2^L lanes per row, XORed by one
+// constant) are distinct slots too, and the key is chosen so that the rows
+// one read instruction gathers do not make it take a second pass (see
+// swz_key).  The padded layout's element-wise scatter lost half its LDS
+// cycles to bank conflicts.  The tiles sit at the same offsets as in the
 // padded layout (a tile's pad is left unused).  16-byte elements keep the
 // padded layout: the same swizzle measured up to 2% slower for them.
 // ---------------------------------------------------------------------------
@@ -502,6 +503,26 @@ template <int S, int B, bool VEC, int NT> constexpr bool lds_swizzled() {
   if (S != 8 || !VEC || Sh::VB != 16) return false;
   constexpr int PT = (Sh::CPT + NT - 1) / NT;
   return Sh::CPT % NT == 0 && PT % 2 == 0;
+}
+
+// The XOR key of LDS row r in the swizzled layout (L = b - 1 slot bits): the
+// physical slot of logical slot c is c ^ key(r).  Writes of 16 bytes are
+// served 8 lanes at a time and need 8 distinct slots modulo 8; reads of 16
+// bytes are served a quarter of a wavefront at a time, and on gfx950 they
+// ran conflict-free only when the four 16-lane groups of one read agree in
+// the key's bits 2-3 (a probe of XOR patterns on 256-byte rows: keys that
+// differ in bits 0-1 between the groups cost nothing, in bit 2 or 3 a
+// second pass).  At b = 5 a wavefront gathers four consecutive rows, so the
+// key keeps bits 2-3 of r and folds bit 3 into bit 0: r ^ (r >> 3); the
+// scatter's eight lanes still land on eight distinct slots modulo 8.  The
+// bit reversal (b = 4, 6) was conflict-free there and stays.
+template <int L> __device__ __forceinline__ uint32_t swz_key(uint32_t r) {
+  const uint32_t lo = r & ((1u << L) - 1u);
+  if constexpr (L == 4) {
+    return lo ^ (lo >> 3);
+  } else {
+    return rev_c<L>(lo);
+  }
 }
 
 template <int S, int B, bool VEC, int NT, int PT>
@@ -517,7 +538,9 @@ __device__ __forceinline__ void tile_scatter_swz(const Chunk<S, 16> (&reg)[PT],
     const int q = (int)threadIdx.x + i * NT;
     const uint32_t x = (uint32_t)(q / Sh::CPR);  // < R/2; chunk i + HALF is row x + R/2
     const uint32_t zc = (uint32_t)(q % Sh::CPR);
-    const uint32_t slot = (rev_c<B>(x) >> 1) ^ zc;
+    // both destination rows rev_b(2 zc) and rev_b(2 zc + 1) are rev_L(zc)
+    // modulo 2^L, so one key serves the two stores
+    const uint32_t slot = (rev_c<B>(x) >> 1) ^ swz_key<L>(rev_c<L>(zc));
     // element j of both chunks, as whole-vector shuffles (a union copy here
     // sends the register arrays to scratch memory)
     const V a = reg[i].v, b = reg[i + HALF].v;
@@ -540,7 +563,7 @@ __device__ __forceinline__ void tile_store_swz(typename Bytes<S>::T* __restrict_
     const int q = (int)threadIdx.x + i * NT;
     const uint32_t r = (uint32_t)(q / Sh::CPR);
     const uint32_t cc = (uint32_t)(q % Sh::CPR);
-    const V v = l[(r << L) + (cc ^ rev_c<L>(r & ((1u << L) - 1u)))];
+    const V v = l[(r << L) + (cc ^ swz_key<L>(r))];
     const uint64_t off = (uint64_t)r * rowstride + (uint64_t)y * Sh::R + (uint64_t)(cc * Sh::CE);
     st_hint<H>(reinterpret_cast<V*>(base + off), v);
   }
@@ -559,7 +582,7 @@ __device__ __forceinline__ void tile_gather_swz(Chunk<S, 16> (&reg)[PT],
     const int q = (int)threadIdx.x + i * NT;
     const uint32_t r = (uint32_t)(q / Sh::CPR);
     const uint32_t cc = (uint32_t)(q % Sh::CPR);
-    reg[i].v = l[(r << L) + (cc ^ rev_c<L>(r & ((1u << L) - 1u)))];
+    reg[i].v = l[(r << L) + (cc ^ swz_key<L>(r))];
   }
 }
 

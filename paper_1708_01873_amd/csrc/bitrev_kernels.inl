@@ -363,6 +363,53 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
   }
 }
 
+// In place, register-staged (complex64): half the threads of k_tile_dit hold
+// the pair in registers; each tile in turn is staged through one LDS tile,
+// takes the levels there and is written over its partner.  Both tiles are
+// read before either is written, and no other workgroup touches them.  One
+// LDS tile per workgroup instead of two lets four workgroups share a compute
+// unit at b = 6 instead of two.
+template <int S, int B, bool VEC, int H>
+__global__ __launch_bounds__((rs_threads<S, B, VEC>())) void k_tile_dit_rs(
+    void* data, int m, uint64_t items_per_seg, uint64_t total_items, uint64_t seg_elems,
+    int stages, int inverse, int order, int xcds) {
+  typedef typename Bytes<S>::T E;
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename ComplexOf<S>::T F;
+  constexpr int NT = rs_threads<S, B, VEC>();
+  constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  __shared__ E lds[Sh::TILE_E];
+  __shared__ F tw[(1 << B) > 1 ? (1 << B) : 2];
+  make_twiddles<S, B, NT>(tw);
+  const uint64_t rowstride = 1ull << (m + B);
+  for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
+    uint64_t seg = 0, local = item;
+    if (items_per_seg != total_items) {
+      seg = item / items_per_seg;
+      local = item - seg * items_per_seg;
+    }
+    E* base = static_cast<E*>(data) + seg * seg_elems;
+    const uint32_t y = inplace_pair_at(m, local, order);
+    const uint32_t yr = rev_bits(y, m);
+    const bool pal = (y == yr);
+    Chunk<S, Sh::VB> ra[PT], rb[PT];
+    tile_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
+    if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
+    tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+    __syncthreads();
+    dit_rows<S, B, NT, 4>(lds, Sh::R, stages, inverse != 0, tw);
+    tile_store<S, B, VEC, NT, PT, H>(base, rowstride, yr, lds);
+    if (!pal) {
+      __syncthreads();  // every row of tile y's result has left LDS
+      tile_scatter<S, B, VEC, NT, PT>(rb, lds);
+      __syncthreads();
+      dit_rows<S, B, NT, 4>(lds, Sh::R, stages, inverse != 0, tw);
+      tile_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds);
+    }
+    __syncthreads();
+  }
+}
+
 // Threads of the rectangular-tile DIT kernel: two 16-byte accesses per
 // thread per tile of 2^(BX+BZ) elements, between 64 and 1024.
 template <int S, int BX, int BZ> constexpr int rect_threads() {
@@ -444,6 +491,14 @@ __global__ __launch_bounds__((rect_threads<S, BX, BZ>())) void k_tile_dit_rect(
 
 template <int S, int B, bool VEC, int H>
 hipError_t run_dit_h(const DitLaunch& a, hipStream_t st) {
+  if constexpr (S == 8) {
+    if (a.rs && a.t.src == a.t.dst) {
+      hipLaunchKernelGGL((k_tile_dit_rs<S, B, VEC, H>), dim3(a.t.grid), dim3(rs_threads<S, B, VEC>()),
+                         0, st, a.t.dst, a.t.m, a.t.items_per_seg, a.t.total_items, a.t.seg_elems,
+                         a.stages, a.inverse, a.t.balanced, a.t.xcds);
+      return hipGetLastError();
+    }
+  }
   if (a.t.src == a.t.dst) {
     hipLaunchKernelGGL((k_tile_dit<S, B, VEC, true, H>), dim3(a.t.grid),
                        dim3(tile_threads<S, B, VEC>()), 0, st, a.t.src, a.t.dst, a.t.m,

@@ -49,6 +49,8 @@ struct DitLaunch {
   int inverse;              // 1: exp(+2 pi i ...) twiddles
   int rect_bz = 0;          // > 0: out of place with rectangular tiles of
                             // 2^b source rows of 2^rect_bz elements
+  int rs = 0;               // 1: in place, complex64, the pair held in
+                            // registers and staged through one LDS tile
 };
 
 struct TransposeLaunch {

@@ -107,6 +107,33 @@ def test_dit_rectangular_tiles(dtype, b, variant):
                 _check(got[r], x.reshape(rows, -1)[r], L, inverse, dtype)
 
 
+@pytest.mark.parametrize("b", [4, 5, 6])
+def test_dit_inplace_register_staged(b):
+    """In place with the tile pair held in registers and its tiles staged
+    through one LDS tile in turn (complex64): every level count up to b,
+    palindromic and paired tiles, several rows, every cache hint, both
+    directions."""
+    dtype = np.complex64
+    for k, rows in ((2 * b, 1), (2 * b + 1, 2), (15, 3), (18, 1)):
+        for L in range(1, b + 1):
+            x = _data(k, rows, dtype, 9000 + 100 * k + 10 * L + b)
+            t = torch.from_numpy(x).cuda().view(rows, 1 << k)
+            inverse = (L + k) % 2 == 0
+            hints = 1 + (L + k + b) % 4
+            br.bitrev_dit_stages(t, t, stages=L, inverse=inverse, tile_bits=b, variant=3,
+                                 cache_hints=hints)
+            got = to_host_bytes(t).view(dtype).reshape(rows, -1)
+            for r in range(rows):
+                _check(got[r], x.reshape(rows, -1)[r], L, inverse, dtype)
+
+
+def test_dit_inplace_register_staged_full_size():
+    x = workloads.complex64_normal(24, workloads.SEEDS["c2"])
+    t = torch.from_numpy(x).cuda()
+    br.bitrev_dit_stages(t, t, stages=6, tile_bits=6, variant=3)
+    _check(to_host_bytes(t).view(np.complex64), x, 6, False, np.complex64)
+
+
 def test_dit_rectangular_tiles_full_size():
     """The complex64 2^24 array at six fused levels on 2^6 x 2^4 tiles."""
     x = workloads.complex64_normal(24, workloads.SEEDS["c2"])
@@ -121,6 +148,10 @@ def test_dit_rectangular_tiles_rejected_where_they_do_not_apply():
         with pytest.raises(br.BitrevError) as e:      # in place
             br.bitrev_dit_stages(t, t, stages=4, **kw)
         assert e.value.status == br.ERROR_NOT_SUPPORTED
+    t2 = torch.zeros(1 << 16, dtype=torch.complex128, device="cuda")
+    with pytest.raises(br.BitrevError) as e:          # register-staged: complex64 only
+        br.bitrev_dit_stages(t2, t2, stages=4, tile_bits=6, variant=3)
+    assert e.value.status == br.ERROR_NOT_SUPPORTED
     with pytest.raises(br.BitrevError) as e:          # b = 4
         br.bitrev_dit_stages(t, stages=4, tile_bits=4, variant=2)
     assert e.value.status == br.ERROR_NOT_SUPPORTED
