@@ -279,35 +279,38 @@ def batched_speedup(torch, br, reps: int):
     }
 
 
-# Where a shifted copy destination starts inside its allocation: with the
+# Where shifted copy destinations start inside their allocation: with the
 # destination at the same offset as the source within their allocations, a
 # linear copy's concurrent reads and writes meet the same memory channels;
-# 1 MiB + 8 KiB in, the 4 GiB copy ran up to 5% faster (write-through form).
-COPY_SHIFT_BYTES = (1 << 20) + 8192
+# 1 MiB + 8 KiB or 17 MiB in, the 4 GiB copy ran up to 5% faster
+# (write-through form; the best offset differed between array sizes).
+COPY_SHIFTS = ((1 << 20) + 8192, 17 << 20)
 
 
 def best_copy(torch, br, timer, x, y, reps: int) -> dict:
     """The fastest reference copy of x (the same bytes as the permutation)
     under the timer's flush policy: the linear streaming copy into y and into
-    a destination shifted by COPY_SHIFT_BYTES, and the copy in the
-    out-of-place tile kernels' order (the identity map, same reads and row
-    shape as the permutation), each in its four cache-hint forms.  Returns
-    the fastest mean step time and which copy gave it."""
+    destinations shifted by COPY_SHIFTS, and the copy in the out-of-place
+    tile kernels' order (the identity map, same reads and row shape as the
+    permutation), each in its four cache-hint forms.  Returns the fastest
+    mean step time and which copy gave it."""
     es = x.element_size()
-    shifted = torch.empty(x.numel() + COPY_SHIFT_BYTES // es, dtype=x.dtype, device=x.device)
-    ys = shifted[COPY_SHIFT_BYTES // es:]
+    n = x.numel()
+    shifted = torch.empty(n + max(COPY_SHIFTS) // es, dtype=x.dtype, device=x.device)
     forms = []
     for h in (1, 2, 3, 4):
         forms.append(("linear", h, lambda h=h: br.bitrev_copy(x, y, cache_hints=h)))
-        forms.append(("linear, shifted destination", h,
-                      lambda h=h: br.bitrev_copy(x, ys, cache_hints=h)))
+        for sh in COPY_SHIFTS:
+            ys = shifted[sh // es: sh // es + n]
+            forms.append(("linear, destination shifted %d KiB" % (sh >> 10), h,
+                          lambda h=h, ys=ys: br.bitrev_copy(x, ys, cache_hints=h)))
         forms.append(("tile order", h, lambda h=h: br.bitrev_copy_tiled(x, y, cache_hints=h)))
     best = None
     for name, h, fn in forms:
         ms = statistics.fmean(timer.time(fn, reps))
         if best is None or ms < best["ms"]:
             best = {"ms": ms, "copy": name, "cache_hints": h}
-    del shifted, ys
+    del shifted
     return best
 
 
