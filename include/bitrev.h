@@ -346,9 +346,10 @@ bitrev_status_t bitrev_digitrev_outofplace_ex(const void* src, void* dst, int lo
  * works on contiguous blocks).  Afterwards every block of 2^stages
  * consecutive outputs J holds the length-2^stages DFT of the subsequence
  * x[rev(J) + 2^(log2n - stages) u], u = 0 .. 2^stages - 1, with twiddles
- * exp(-2 pi i / 2^s) (inverse = 1: exp(+2 pi i / 2^s), unscaled).  The levels
- * run on the tile rows staged in LDS, so the HBM traffic is that of the plain
- * permutation.  src == dst is in place; otherwise the ranges must not overlap.
+ * exp(-2 pi i / 2^s) (inverse = 1: exp(+2 pi i / 2^s), unscaled).  The first
+ * levels (up to three, where a thread's loads hold whole blocks of them) run
+ * in registers between the loads and the LDS stage, the others on the tile
+ * rows staged in LDS, so the HBM traffic is that of the plain permutation.  src == dst is in place; otherwise the ranges must not overlap.
  * 0 <= stages <= min(floor(log2n / 2), 6), else BITREV_ERROR_NOT_SUPPORTED;
  * stages = 0 is bitrev_rows.  Arithmetic in the element's precision with
  * twiddles rounded once from double precision. */
@@ -366,7 +367,7 @@ bitrev_status_t bitrev_dit_stages(const void* src, void* dst, int log2n, int64_t
  * BITREV_ERROR_NOT_SUPPORTED.  In place (square tiles only: a rectangular
  * tile's image is not a tile of the same shape) variant 3 keeps the tile
  * pair in registers and stages its tiles through one LDS tile in turn, with
- * half the threads (complex64 only, else BITREV_ERROR_NOT_SUPPORTED);
+ * half the threads (2b <= log2n, else BITREV_ERROR_NOT_SUPPORTED);
  * variant 2 in place returns BITREV_ERROR_NOT_SUPPORTED.  stages = 0 runs bitrev_rows_ex with this
  * config, its variant ignored (and a tile width too wide for square tiles
  * left to the plan). */

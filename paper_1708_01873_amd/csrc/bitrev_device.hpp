@@ -102,6 +102,13 @@ __host__ __device__ __forceinline__ uint32_t rev_bits(uint32_t v, int j) {
   return (uint32_t)(((uint64_t)__builtin_bitreverse32(v)) >> (32 - j));
 }
 
+// rev_p(v) at compile time (chunk-to-position maps of unrolled loops).
+__host__ __device__ constexpr int crev(int v, int p) {
+  int r = 0;
+  for (int i = 0; i < p; ++i) r |= ((v >> i) & 1) << (p - 1 - i);
+  return r;
+}
+
 template <int J> __host__ __device__ __forceinline__ uint32_t rev_c(uint32_t v) {
   if constexpr (J == 0) {
     return 0u;
@@ -460,6 +467,72 @@ __device__ __forceinline__ void tile_store(typename Bytes<S>::T* __restrict__ ba
   }
 }
 
+// tile_load, tile_scatter (bit reversal) and tile_store for thread counts
+// that are a multiple of the accesses per row: thread t's chunk i is then
+// row x0 + i NT / CPR (x0 = t / CPR, the top log2 PT bits of the row index
+// are i) at chunk t % CPR, so every address is one per-thread base plus
+// uniform steps and immediate offsets.  (From the general forms the
+// compiler keeps PT 64-bit row offsets live across the item loop.)
+template <int S, int B, bool VEC, int NT, int PT>
+constexpr bool tile_rows_strided() {
+  typedef TileShape<S, B, VEC> Sh;
+  return Sh::CPT == NT * PT && NT % Sh::CPR == 0 && (PT & (PT - 1)) == 0;
+}
+
+template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
+__device__ __forceinline__ void tile_load_rows(Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                               const typename Bytes<S>::T* __restrict__ base,
+                                               uint64_t rowstride, uint32_t y) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<Sh::VB>::T V;
+  static_assert(tile_rows_strided<S, B, VEC, NT, PT>(), "strided row assignment");
+  const uint32_t t = threadIdx.x;
+  const typename Bytes<S>::T* p = base + (uint64_t)(t / Sh::CPR) * rowstride +
+                                  (uint64_t)y * Sh::R + (t % Sh::CPR) * Sh::CE;
+#pragma unroll
+  for (int i = 0; i < PT; ++i)
+    reg[i].v = ld_hint<H>(reinterpret_cast<const V*>(p + (uint64_t)i * (NT / Sh::CPR) * rowstride));
+}
+
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void tile_scatter_rows(
+    const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT], typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  static_assert(tile_rows_strided<S, B, VEC, NT, PT>(), "strided row assignment");
+  constexpr int LPT = PT >= 8 ? 3 : (PT == 4 ? 2 : (PT == 2 ? 1 : 0));
+  static_assert((1 << LPT) == PT, "two to eight chunks per thread");
+  const uint32_t t = threadIdx.x;
+  // source (x, z) -> LDS row rev_B(z), column rev_B(x); x = x0 + i 2^(B-LPT)
+  // has column rev_B(x0) + rev_LPT(i)
+  const uint32_t col0 = rev_c<B>(t / Sh::CPR);
+#pragma unroll
+  for (int j = 0; j < Sh::CE; ++j) {
+    typename Bytes<S>::T* lrow = lds + rev_c<B>((t % Sh::CPR) * Sh::CE + j) * Sh::PE + col0;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) lrow[crev(i, LPT)] = reg[i].e[j];
+  }
+}
+
+template <int S, int B, bool VEC, int NT, int PT, int H = kHintPlain>
+__device__ __forceinline__ void tile_store_rows(typename Bytes<S>::T* __restrict__ base,
+                                                uint64_t rowstride, uint32_t y,
+                                                const typename Bytes<S>::T* lds) {
+  typedef TileShape<S, B, VEC> Sh;
+  typedef typename Bytes<Sh::VB>::T V;
+  static_assert(tile_rows_strided<S, B, VEC, NT, PT>(), "strided row assignment");
+  const uint32_t t = threadIdx.x;
+  const uint32_t r0 = t / Sh::CPR, cc = t % Sh::CPR;
+  const typename Bytes<S>::T* l = lds + r0 * Sh::PE + cc * Sh::CE;
+  typename Bytes<S>::T* p = base + (uint64_t)r0 * rowstride + (uint64_t)y * Sh::R + cc * Sh::CE;
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    Chunk<S, Sh::VB> c;
+#pragma unroll
+    for (int j = 0; j < Sh::CE; ++j) c.e[j] = l[i * (NT / Sh::CPR) * Sh::PE + j];
+    st_hint<H>(reinterpret_cast<V*>(p + (uint64_t)i * (NT / Sh::CPR) * rowstride), c.v);
+  }
+}
+
 // LDS -> registers in the order tile_store writes: chunk i of this thread
 // is LDS row r, chunk cc (destination row r of the tile).
 template <int S, int B, bool VEC, int NT, int PT>
@@ -809,7 +882,7 @@ __device__ __forceinline__ void make_twiddles(typename ComplexOf<S>::T* tw) {
   }
 }
 
-// Levels 1 .. stages of the radix-2 DIT butterflies on `rows` staged rows
+// Levels FIRST .. stages of the radix-2 DIT butterflies on `rows` staged rows
 // of 2^b elements (a power of two: 2^b or 2^(b+1) for square tiles, fewer
 // for rectangular ones): for blocks of 2^s, (a, b) -> (a + w^t b, a - w^t b),
 // w = exp(-+ 2 pi i / 2^s) (sign + for the inverse).  Up to three levels run
@@ -842,7 +915,7 @@ __device__ __forceinline__ void rot_quarter(F wr, F wi, F sg, F* rr, F* ri) {
   *ri = -sg * wr;
 }
 
-template <int S, int B, int NT, int MAXR = 8>
+template <int S, int B, int NT, int MAXR = 8, int FIRST = 1>
 __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, int stages,
                                          bool inverse, const typename ComplexOf<S>::T* tw) {
   typedef typename ComplexOf<S>::T F;
@@ -851,7 +924,7 @@ __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, in
   F* base = reinterpret_cast<F*>(lds);
   const F sg = inverse ? (F)-1 : (F)1;  // conjugates the forward twiddles
   const int rsh = 31 - __builtin_clz((unsigned)rows);  // rows is a power of two
-  int s = 1;
+  int s = FIRST;
   while (s <= stages) {
     const int h = 1 << (s - 1);
     if (MAXR >= 8 && s + 2 <= stages) {
@@ -935,6 +1008,119 @@ __device__ __forceinline__ void dit_rows(typename Bytes<S>::T* lds, int rows, in
     }
     __syncthreads();
   }
+}
+
+// The first levels of the DIT on values still in registers.  A tile thread
+// whose PT = 2^p accesses cover rows x0 + i 2^(B-p) (i < PT) of one column
+// holds, for each element of its chunks, the values that land on the 2^p
+// consecutive destination positions rev_B(x) = rev_p(i) + 2^p rev_(B-p)(x0)
+// of one destination row: a whole block of levels 1 .. p, whose twiddles
+// w_2^0, w_4^{0,1} and w_8^{0..3} are constants (1, -+i and
+// (+-1 -+ i)/sqrt 2).  Doing those levels here, between the loads and the
+// scatter into LDS, saves dit_rows their passes over LDS (dit_rows then
+// starts at level p + 1).  The arithmetic per butterfly is that of bfly.
+template <int CPT, int CPR, int NT> constexpr int dit_reg_levels_of() {
+  constexpr int PT = CPT / NT;
+  return (CPT % NT != 0 || NT % CPR != 0 || PT < 2) ? 0 : (PT >= 8 ? 3 : (PT >= 4 ? 2 : 1));
+}
+
+template <typename F, int P, int LV>
+__device__ __forceinline__ void dit_block_levels(F (&re)[P], F (&im)[P], F sg) {
+  constexpr F C = (F)0.70710678118654752440084436210484904;
+#pragma unroll
+  for (int s = 1; s <= LV; ++s) {
+    const int h = 1 << (s - 1);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (q & h) continue;
+      const int t = q & (h - 1);  // twiddle w_{2h}^t
+      const F br = re[q + h], bi = im[q + h];
+      F tr, ti;
+      if (t == 0) {
+        tr = br;
+        ti = bi;
+      } else if (2 * t == h) {  // w = -+ i
+        tr = sg * bi;
+        ti = -sg * br;
+      } else {  // h = 4, t = 1 or 3
+        const F wr = t == 1 ? C : -C, wi = -sg * C;
+        tr = br * wr - bi * wi;
+        ti = br * wi + bi * wr;
+      }
+      re[q + h] = re[q] - tr;
+      im[q + h] = im[q] - ti;
+      re[q] = re[q] + tr;
+      im[q] = im[q] + ti;
+    }
+  }
+}
+
+// Levels 1 .. LV (LV <= p = log2 PT <= 3; see above) on a thread's chunks,
+// in place: chunk i keeps row x0 + i 2^(B-p).
+template <int S, int VB, int PT, int LV>
+__device__ __forceinline__ void dit_reg_levels_n(Chunk<S, VB> (&reg)[PT], bool inverse) {
+  typedef typename ComplexOf<S>::T F;
+  static_assert(PT == 2 || PT == 4 || PT == 8, "two, four or eight rows per thread");
+  constexpr int p = PT == 8 ? 3 : (PT == 4 ? 2 : 1);
+  static_assert(LV >= 1 && LV <= p, "levels held by the thread's rows");
+  constexpr int CE = VB / S;
+  const F sg = inverse ? (F)-1 : (F)1;
+#pragma unroll
+  for (int e = 0; e < CE; ++e) {
+    F re[PT], im[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      Cplx<F> c;
+      __builtin_memcpy(&c, &reg[crev(q, p)].e[e], sizeof(c));
+      re[q] = c.re;
+      im[q] = c.im;
+    }
+    dit_block_levels<F, PT, LV>(re, im, sg);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const Cplx<F> c{re[q], im[q]};
+      __builtin_memcpy(&reg[crev(q, p)].e[e], &c, sizeof(c));
+    }
+  }
+}
+
+// LDS passes dit_rows makes for `levels` levels: radix 8 (MAXR 8) while
+// three or more remain, then radix 4, then radix 2.
+__host__ __device__ constexpr int dit_passes(int levels, int maxr) {
+  int p = 0;
+  while (levels > 0) {
+    levels -= (maxr >= 8 && levels >= 3) ? 3 : (levels >= 2 ? 2 : 1);
+    ++p;
+  }
+  return p;
+}
+
+// Whether the first PRE levels go to registers: only where that saves
+// dit_rows a pass over LDS (at five levels, radix 8 + 4 after none and
+// 4 + 4 after one are both two passes, and the radix-8 form measured 1%
+// faster).
+__host__ __device__ constexpr bool dit_pre_pays(int stages, int pre, int maxr) {
+  return pre > 0 && stages >= pre && dit_passes(stages - pre, maxr) < dit_passes(stages, maxr);
+}
+
+// Levels 1 .. log2 PT on a thread's chunks when `apply` (uniform).
+template <int S, int VB, int PT>
+__device__ __forceinline__ void dit_reg_levels(Chunk<S, VB> (&reg)[PT], bool apply, bool inverse) {
+  constexpr int p = PT == 8 ? 3 : (PT == 4 ? 2 : 1);
+  if (apply) dit_reg_levels_n<S, VB, PT, p>(reg, inverse);
+}
+
+// dit_rows from level 1, or from level PRE + 1 after the register levels
+// (the first level a compile-time constant either way: a run-time first
+// level cost the two-tile kernels 1% at three and five levels).
+template <int S, int B, int NT, int MAXR, int PRE>
+__device__ __forceinline__ void dit_rows_after(typename Bytes<S>::T* lds, int rows, int stages,
+                                               bool inverse, const typename ComplexOf<S>::T* tw,
+                                               bool pre) {
+  if constexpr (PRE > 0) {
+    if (pre) return dit_rows<S, B, NT, MAXR, PRE + 1>(lds, rows, stages, inverse, tw);
+  }
+  dit_rows<S, B, NT, MAXR, 1>(lds, rows, stages, inverse, tw);
 }
 
 // ---------------------------------------------------------------------------

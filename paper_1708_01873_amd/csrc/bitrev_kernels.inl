@@ -315,6 +315,38 @@ __global__ __launch_bounds__(512) void k_block_recursive(void* data, int h, uint
 template <int S, int B, bool INPLACE>
 constexpr int dit_max_radix() { return (S == 8 && !(INPLACE && B >= 6)) ? 8 : 4; }
 
+// Tile steps of the register-staged DIT kernel: the strided-row forms where
+// the thread count allows them (fewer registers held across the item loop;
+// the two-tile kernel measured 1% slower with them at three and five
+// levels, and keeps the general forms).
+template <int S, int B, bool VEC, int NT, int PT, int H>
+__device__ __forceinline__ void dit_load(Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                         const typename Bytes<S>::T* base, uint64_t rowstride,
+                                         uint32_t y) {
+  if constexpr (tile_rows_strided<S, B, VEC, NT, PT>())
+    tile_load_rows<S, B, VEC, NT, PT, H>(reg, base, rowstride, y);
+  else
+    tile_load<S, B, VEC, NT, PT, H>(reg, base, rowstride, y);
+}
+
+template <int S, int B, bool VEC, int NT, int PT>
+__device__ __forceinline__ void dit_scatter(const Chunk<S, TileShape<S, B, VEC>::VB> (&reg)[PT],
+                                            typename Bytes<S>::T* lds) {
+  if constexpr (tile_rows_strided<S, B, VEC, NT, PT>())
+    tile_scatter_rows<S, B, VEC, NT, PT>(reg, lds);
+  else
+    tile_scatter<S, B, VEC, NT, PT>(reg, lds);
+}
+
+template <int S, int B, bool VEC, int NT, int PT, int H>
+__device__ __forceinline__ void dit_store(typename Bytes<S>::T* base, uint64_t rowstride,
+                                          uint32_t y, const typename Bytes<S>::T* lds) {
+  if constexpr (tile_rows_strided<S, B, VEC, NT, PT>())
+    tile_store_rows<S, B, VEC, NT, PT, H>(base, rowstride, y, lds);
+  else
+    tile_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds);
+}
+
 template <int S, int B, bool VEC, bool INPLACE, int H>
 __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
     const void* src, void* dst, int m, uint64_t items_per_seg, uint64_t total_items,
@@ -324,10 +356,13 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
   typedef typename ComplexOf<S>::T F;
   constexpr int NT = tile_threads<S, B, VEC>();
   constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  constexpr int PRE = dit_reg_levels_of<Sh::CPT, Sh::CPR, NT>();
   __shared__ E lds[(INPLACE ? 2 : 1) * Sh::TILE_E];
   __shared__ F tw[(1 << B) > 1 ? (1 << B) : 2];
   make_twiddles<S, B, NT>(tw);
   const uint64_t rowstride = 1ull << (m + B);
+  constexpr int MAXR = dit_max_radix<S, B, INPLACE>();
+  const bool pre = dit_pre_pays(stages, PRE, MAXR);  // levels 1 .. PRE in registers
   for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
     uint64_t seg = 0, local = item;
     if (items_per_seg != total_items) {
@@ -344,33 +379,45 @@ __global__ __launch_bounds__((tile_threads<S, B, VEC>())) void k_tile_dit(
       const bool pal = (y == yr);
       tile_load<S, B, VEC, NT, PT, H>(ra, in, rowstride, y);
       if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, in, rowstride, yr);
+      if constexpr (PRE > 0) {
+        dit_reg_levels<S, Sh::VB, PT>(ra, pre, inverse != 0);
+        if (!pal) dit_reg_levels<S, Sh::VB, PT>(rb, pre, inverse != 0);
+      }
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       if (!pal) tile_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
       __syncthreads();
-      dit_rows<S, B, NT, dit_max_radix<S, B, true>()>(lds, pal ? Sh::R : 2 * Sh::R, stages,
-                                                        inverse != 0, tw);
+      dit_rows_after<S, B, NT, MAXR, PRE>(lds, pal ? Sh::R : 2 * Sh::R, stages, inverse != 0, tw,
+                                          pre);
       if (!pal) tile_store<S, B, VEC, NT, PT, H>(out, rowstride, y, lds + Sh::TILE_E);
       tile_store<S, B, VEC, NT, PT, H>(out, rowstride, yr, lds);
     } else {
       const uint32_t y = oop_tile_at(m, (uint32_t)local, order);
       tile_load<S, B, VEC, NT, PT, H>(ra, in, rowstride, y);
+      if constexpr (PRE > 0) dit_reg_levels<S, Sh::VB, PT>(ra, pre, inverse != 0);
       tile_scatter<S, B, VEC, NT, PT>(ra, lds);
       __syncthreads();
-      dit_rows<S, B, NT, dit_max_radix<S, B, false>()>(lds, Sh::R, stages, inverse != 0, tw);
+      dit_rows_after<S, B, NT, MAXR, PRE>(lds, Sh::R, stages, inverse != 0, tw, pre);
       tile_store<S, B, VEC, NT, PT, H>(out, rowstride, rev_bits(y, m), lds);
     }
     __syncthreads();
   }
 }
 
-// In place, register-staged (complex64): half the threads of k_tile_dit hold
+// Waves per SIMD the register-staged DIT kernel is compiled for: as many as
+// the LDS lets workgroups share a compute unit where the registers allow
+// (complex64 b = 6: four workgroups of 33.5 KiB; complex128 b = 6: two).
+template <int S, int B, bool VEC> constexpr int rs_dit_waves() {
+  return S == 16 ? 4 : ((B == 6 && VEC) ? 8 : 6);
+}
+
+// In place, register-staged: half the threads of k_tile_dit hold
 // the pair in registers; each tile in turn is staged through one LDS tile,
 // takes the levels there and is written over its partner.  Both tiles are
 // read before either is written, and no other workgroup touches them.  One
 // LDS tile per workgroup instead of two lets four workgroups share a compute
 // unit at b = 6 instead of two.
 template <int S, int B, bool VEC, int H>
-__global__ __launch_bounds__((rs_threads<S, B, VEC>())) void k_tile_dit_rs(
+__global__ __launch_bounds__((rs_threads<S, B, VEC>()), (rs_dit_waves<S, B, VEC>())) void k_tile_dit_rs(
     void* data, int m, uint64_t items_per_seg, uint64_t total_items, uint64_t seg_elems,
     int stages, int inverse, int order, int xcds) {
   typedef typename Bytes<S>::T E;
@@ -378,10 +425,12 @@ __global__ __launch_bounds__((rs_threads<S, B, VEC>())) void k_tile_dit_rs(
   typedef typename ComplexOf<S>::T F;
   constexpr int NT = rs_threads<S, B, VEC>();
   constexpr int PT = (Sh::CPT + NT - 1) / NT;
+  constexpr int PRE = dit_reg_levels_of<Sh::CPT, Sh::CPR, NT>();
   __shared__ E lds[Sh::TILE_E];
   __shared__ F tw[(1 << B) > 1 ? (1 << B) : 2];
   make_twiddles<S, B, NT>(tw);
   const uint64_t rowstride = 1ull << (m + B);
+  const bool pre = dit_pre_pays(stages, PRE, 4);  // levels 1 .. PRE in registers
   for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
     uint64_t seg = 0, local = item;
     if (items_per_seg != total_items) {
@@ -393,27 +442,39 @@ __global__ __launch_bounds__((rs_threads<S, B, VEC>())) void k_tile_dit_rs(
     const uint32_t yr = rev_bits(y, m);
     const bool pal = (y == yr);
     Chunk<S, Sh::VB> ra[PT], rb[PT];
-    tile_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
-    if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
-    tile_scatter<S, B, VEC, NT, PT>(ra, lds);
+    dit_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
+    if (!pal) dit_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
+    if constexpr (PRE > 0) dit_reg_levels<S, Sh::VB, PT>(ra, pre, inverse != 0);
+    dit_scatter<S, B, VEC, NT, PT>(ra, lds);
     __syncthreads();
-    dit_rows<S, B, NT, 4>(lds, Sh::R, stages, inverse != 0, tw);
-    tile_store<S, B, VEC, NT, PT, H>(base, rowstride, yr, lds);
+    dit_rows_after<S, B, NT, 4, PRE>(lds, Sh::R, stages, inverse != 0, tw, pre);
+    dit_store<S, B, VEC, NT, PT, H>(base, rowstride, yr, lds);
     if (!pal) {
+      if constexpr (PRE > 0) dit_reg_levels<S, Sh::VB, PT>(rb, pre, inverse != 0);
       __syncthreads();  // every row of tile y's result has left LDS
-      tile_scatter<S, B, VEC, NT, PT>(rb, lds);
+      dit_scatter<S, B, VEC, NT, PT>(rb, lds);
       __syncthreads();
-      dit_rows<S, B, NT, 4>(lds, Sh::R, stages, inverse != 0, tw);
-      tile_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds);
+      dit_rows_after<S, B, NT, 4, PRE>(lds, Sh::R, stages, inverse != 0, tw, pre);
+      dit_store<S, B, VEC, NT, PT, H>(base, rowstride, y, lds);
     }
     __syncthreads();
   }
 }
 
-// Threads of the rectangular-tile DIT kernel: two 16-byte accesses per
-// thread per tile of 2^(BX+BZ) elements, between 64 and 1024.
+// 16-byte accesses per thread per tile of the rectangular-tile DIT kernel:
+// a thread's accesses are rows 2^BX / PT apart, so that the first log2 PT
+// levels run in registers.  Measured per shape (alternating rounds, six
+// levels out of place at 2^24 and 2^26): complex64 eight (three levels in
+// registers); complex128 four at BX = 6 (eight held 18 more registers and
+// ran 1-3% slower), two at BX = 5 (four or eight cost 1-3% at four and five
+// levels).
+template <int S, int BX, int BZ> constexpr int rect_pt() {
+  return S == 16 ? (BX == 5 ? 2 : 4) : 8;
+}
+
+// Threads of the rectangular-tile DIT kernel, between 64 and 1024.
 template <int S, int BX, int BZ> constexpr int rect_threads() {
-  constexpr int c = ((1 << (BX + BZ)) * S / 16) / 2;
+  constexpr int c = ((1 << (BX + BZ)) * S / 16) / rect_pt<S, BX, BZ>();
   return c < 64 ? 64 : (c > 1024 ? 1024 : c);
 }
 
@@ -440,13 +501,19 @@ __global__ __launch_bounds__((rect_threads<S, BX, BZ>())) void k_tile_dit_rect(
   constexpr int CPT = RX * SRC_CPR;       // accesses per tile (either side)
   constexpr int NT = rect_threads<S, BX, BZ>();
   constexpr int PT = CPT / NT;
+  constexpr int LPT = PT == 8 ? 3 : (PT == 4 ? 2 : (PT == 2 ? 1 : 0));  // log2 PT
   constexpr int PE = TileShape<S, BX, true>::PE;  // padded LDS row pitch
-  static_assert(SRC_CPR >= 1 && CPT % NT == 0, "rectangular tile shape");
+  constexpr int PRE = dit_reg_levels_of<CPT, SRC_CPR, NT>();
+  static_assert(SRC_CPR >= 1 && CPT % NT == 0 && NT % SRC_CPR == 0 && NT % DST_CPR == 0 &&
+                    (PT & (PT - 1)) == 0 && PT <= 8,
+                "rectangular tile shape");
   __shared__ E lds[RZ * PE];
   __shared__ F tw[RX];
   make_twiddles<S, BX, NT>(tw);
   const uint64_t src_stride = 1ull << (m + BZ);
   const uint64_t dst_stride = 1ull << (m + BX);
+  constexpr int MAXR = dit_max_radix<S, BX, false>();
+  const bool pre = dit_pre_pays(stages, PRE, MAXR);  // levels 1 .. PRE in registers
   for (uint64_t item = xcd_block(xcds); item < total_items; item += gridDim.x) {
     uint64_t seg = 0, local = item;
     if (items_per_seg != total_items) {
@@ -456,34 +523,38 @@ __global__ __launch_bounds__((rect_threads<S, BX, BZ>())) void k_tile_dit_rect(
     const E* in = static_cast<const E*>(src) + seg * seg_elems;
     E* out = static_cast<E*>(dst) + seg * seg_elems;
     const uint32_t y = oop_tile_at(m, (uint32_t)local, order);
+    // thread t reads rows x0 + i 2^BX / PT (i < PT) at column chunk zc and
+    // writes destination rows r0 + i NT / DST_CPR at chunk cc: one base
+    // address per side, the rest uniform steps and immediate offsets
+    const uint32_t t = threadIdx.x;
+    const uint32_t x0 = t / SRC_CPR, zc = t % SRC_CPR;
+    const E* pin = in + (uint64_t)x0 * src_stride + (uint64_t)y * RZ + zc * CE;
     Chunk<S, 16> reg[PT];
 #pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const int q = (int)threadIdx.x + i * NT;
-      const uint32_t x = (uint32_t)(q / SRC_CPR), zc = (uint32_t)(q % SRC_CPR);
-      reg[i].v = ld_hint<H>(reinterpret_cast<const V*>(
-          in + (uint64_t)x * src_stride + (uint64_t)y * RZ + zc * CE));
-    }
+    for (int i = 0; i < PT; ++i)
+      reg[i].v = ld_hint<H>(reinterpret_cast<const V*>(pin + (uint64_t)i * (RX / PT) * src_stride));
+    if constexpr (PRE > 0) dit_reg_levels<S, 16, PT>(reg, pre, inverse != 0);
+    // source (x, z) goes to LDS row rev_BZ(z), column rev_BX(x); with
+    // x = x0 + i 2^(BX-LPT) the column is rev_BX(x0) + rev_LPT(i)
+    const uint32_t col0 = rev_c<BX>(x0);
 #pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const int q = (int)threadIdx.x + i * NT;
-      const uint32_t x = (uint32_t)(q / SRC_CPR), zc = (uint32_t)(q % SRC_CPR);
-      const uint32_t col = rev_c<BX>(x);
+    for (int j = 0; j < CE; ++j) {
+      E* lrow = lds + rev_c<BZ>(zc * CE + j) * PE + col0;
 #pragma unroll
-      for (int j = 0; j < CE; ++j) lds[rev_c<BZ>(zc * CE + j) * PE + col] = reg[i].e[j];
+      for (int i = 0; i < PT; ++i) lrow[crev(i, LPT)] = reg[i].e[j];
     }
     __syncthreads();
-    dit_rows<S, BX, NT, dit_max_radix<S, BX, false>()>(lds, RZ, stages, inverse != 0, tw);
+    dit_rows_after<S, BX, NT, MAXR, PRE>(lds, RZ, stages, inverse != 0, tw, pre);
     const uint32_t yr = rev_bits(y, m);
+    const uint32_t r0 = t / DST_CPR, cc = t % DST_CPR;
+    const E* lsrc = lds + r0 * PE + cc * CE;
+    E* pout = out + (uint64_t)r0 * dst_stride + (uint64_t)yr * RX + cc * CE;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
-      const int q = (int)threadIdx.x + i * NT;
-      const uint32_t r = (uint32_t)(q / DST_CPR), cc = (uint32_t)(q % DST_CPR);
       Chunk<S, 16> c;
 #pragma unroll
-      for (int j = 0; j < CE; ++j) c.e[j] = lds[r * PE + cc * CE + j];
-      st_hint<H>(reinterpret_cast<V*>(out + (uint64_t)r * dst_stride + (uint64_t)yr * RX + cc * CE),
-                 c.v);
+      for (int j = 0; j < CE; ++j) c.e[j] = lsrc[i * (NT / DST_CPR) * PE + j];
+      st_hint<H>(reinterpret_cast<V*>(pout + (uint64_t)i * (NT / DST_CPR) * dst_stride), c.v);
     }
     __syncthreads();
   }
@@ -491,13 +562,11 @@ __global__ __launch_bounds__((rect_threads<S, BX, BZ>())) void k_tile_dit_rect(
 
 template <int S, int B, bool VEC, int H>
 hipError_t run_dit_h(const DitLaunch& a, hipStream_t st) {
-  if constexpr (S == 8) {
-    if (a.rs && a.t.src == a.t.dst) {
-      hipLaunchKernelGGL((k_tile_dit_rs<S, B, VEC, H>), dim3(a.t.grid), dim3(rs_threads<S, B, VEC>()),
-                         0, st, a.t.dst, a.t.m, a.t.items_per_seg, a.t.total_items, a.t.seg_elems,
-                         a.stages, a.inverse, a.t.balanced, a.t.xcds);
-      return hipGetLastError();
-    }
+  if (a.rs && a.t.src == a.t.dst) {
+    hipLaunchKernelGGL((k_tile_dit_rs<S, B, VEC, H>), dim3(a.t.grid), dim3(rs_threads<S, B, VEC>()),
+                       0, st, a.t.dst, a.t.m, a.t.items_per_seg, a.t.total_items, a.t.seg_elems,
+                       a.stages, a.inverse, a.t.balanced, a.t.xcds);
+    return hipGetLastError();
   }
   if (a.t.src == a.t.dst) {
     hipLaunchKernelGGL((k_tile_dit<S, B, VEC, true, H>), dim3(a.t.grid),

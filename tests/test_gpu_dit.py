@@ -107,13 +107,14 @@ def test_dit_rectangular_tiles(dtype, b, variant):
                 _check(got[r], x.reshape(rows, -1)[r], L, inverse, dtype)
 
 
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
 @pytest.mark.parametrize("b", [4, 5, 6])
-def test_dit_inplace_register_staged(b):
+def test_dit_inplace_register_staged(b, dtype):
     """In place with the tile pair held in registers and its tiles staged
-    through one LDS tile in turn (complex64): every level count up to b,
+    through one LDS tile in turn: every level count up to b (the first
+    levels in registers from the level count that the thread's rows hold),
     palindromic and paired tiles, several rows, every cache hint, both
     directions."""
-    dtype = np.complex64
     for k, rows in ((2 * b, 1), (2 * b + 1, 2), (15, 3), (18, 1)):
         for L in range(1, b + 1):
             x = _data(k, rows, dtype, 9000 + 100 * k + 10 * L + b)
@@ -134,6 +135,15 @@ def test_dit_inplace_register_staged_full_size():
     _check(to_host_bytes(t).view(np.complex64), x, 6, False, np.complex64)
 
 
+def test_dit_inplace_register_staged_complex128_large():
+    """Complex double, 2^22 elements (64 MiB, 2^10 tile pairs) at six levels
+    in place, register-staged, inverse."""
+    x = _data(22, 1, np.complex128, 77)
+    t = torch.from_numpy(x).cuda()
+    br.bitrev_dit_stages(t, t, stages=6, tile_bits=6, variant=3, inverse=True)
+    _check(to_host_bytes(t).view(np.complex128), x, 6, True, np.complex128)
+
+
 def test_dit_rectangular_tiles_full_size():
     """The complex64 2^24 array at six fused levels on 2^6 x 2^4 tiles."""
     x = workloads.complex64_normal(24, workloads.SEEDS["c2"])
@@ -148,8 +158,8 @@ def test_dit_rectangular_tiles_rejected_where_they_do_not_apply():
         with pytest.raises(br.BitrevError) as e:      # in place
             br.bitrev_dit_stages(t, t, stages=4, **kw)
         assert e.value.status == br.ERROR_NOT_SUPPORTED
-    t2 = torch.zeros(1 << 16, dtype=torch.complex128, device="cuda")
-    with pytest.raises(br.BitrevError) as e:          # register-staged: complex64 only
+    t2 = torch.zeros(1 << 10, dtype=torch.complex128, device="cuda")
+    with pytest.raises(br.BitrevError) as e:          # register-staged: square tiles, 2b <= k
         br.bitrev_dit_stages(t2, t2, stages=4, tile_bits=6, variant=3)
     assert e.value.status == br.ERROR_NOT_SUPPORTED
     with pytest.raises(br.BitrevError) as e:          # b = 4
