@@ -803,8 +803,12 @@ __device__ __forceinline__ void tile_outofplace_elem(const typename Bytes<S>::T*
 
 // In place: swap tiles y and yr = rev_m(y) of the array at `base` (one tile
 // when y is a palindrome).  Ends with the LDS free for the next item only
-// after the caller's barrier.
-template <int S, int B, bool VEC, int NT, int H = kHintPlain>
+// after the caller's barrier.  SERIAL: the partner's loads are issued only
+// once tile y has arrived and is scattered, rather than together with tile
+// y's.  Alternating rounds, kernel time, caches evicted: at b = 5 +1.6%
+// (complex64 2^24) and +0.6% (complex128 2^28); at b = 6 -1.3% (complex64
+// 2^26) to +1% (float32 2^30), so b = 6 keeps the joint loads.
+template <int S, int B, bool VEC, int NT, int H = kHintPlain, bool SERIAL = (B <= 5)>
 __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restrict__ base, int m,
                                                   uint32_t y, typename Bytes<S>::T* lds) {
   if constexpr (tile_elementwise<S, B, VEC, NT>()) {
@@ -818,9 +822,17 @@ __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restri
   const bool pal = (yr == y);
   Chunk<S, Sh::VB> ra[PT], rb[PT];
   tile_load<S, B, VEC, NT, PT, H>(ra, base, rowstride, y);
-  if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
-  rev_scatter<S, B, VEC, NT, PT>(ra, lds);
-  if (!pal) rev_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+  if constexpr (SERIAL) {
+    rev_scatter<S, B, VEC, NT, PT>(ra, lds);
+    if (!pal) {
+      tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
+      rev_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+    }
+  } else {
+    if (!pal) tile_load<S, B, VEC, NT, PT, H>(rb, base, rowstride, yr);
+    rev_scatter<S, B, VEC, NT, PT>(ra, lds);
+    if (!pal) rev_scatter<S, B, VEC, NT, PT>(rb, lds + Sh::TILE_E);
+  }
   __syncthreads();
   // tile y first, then its partner: measured a few percent faster than the
   // other order for arrays that fit the Infinity Cache

@@ -762,7 +762,7 @@ __global__ __launch_bounds__((tile_threads<S, B, true>())) void k_batched(
       if ((reinterpret_cast<uintptr_t>(base) & 15u) == 0) {
         // streaming loads, write-through stores: 4096 complex64 arrays of
         // 2^8-2^20 elements 2.017 -> 1.947 ms (streaming stores: no gain)
-        tile_pair_inplace<S, B, true, NT, kHintStreamWriteThrough>(base, m, y, lds);
+        tile_pair_inplace<S, B, true, NT, kHintStreamWriteThrough, false>(base, m, y, lds);
       } else {
         tile_pair_inplace_elem<S, B, NT, 1>(base, m, y, lds);
       }
