@@ -128,6 +128,35 @@ def test_dit_inplace_register_staged(b, dtype):
                 _check(got[r], x.reshape(rows, -1)[r], L, inverse, dtype)
 
 
+@pytest.mark.parametrize("b", [4, 5, 6])
+def test_dit_element_aligned(b):
+    """Complex64 arrays 8 bytes off the 16-byte grid take the element-wise
+    tile accesses (and, in the register-staged kernel, eight one-element
+    chunks per thread: three levels in registers): square tiles in and out
+    of place and register-staged in place, every level count up to b, both
+    directions."""
+    dtype = np.complex64
+    k, rows = 2 * b + 3, 2
+    n = rows << k
+    for L in range(1, b + 1):
+        x = _data(k, rows, dtype, 4000 + 10 * b + L)
+        inverse = L % 2 == 1
+        src = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+        dst = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+        src[1:] = torch.from_numpy(x).cuda()
+        s1, d1 = src[1:].view(rows, 1 << k), dst[1:].view(rows, 1 << k)
+        br.bitrev_dit_stages(s1, d1, stages=L, inverse=inverse, tile_bits=b, variant=1)
+        got = to_host_bytes(d1).view(dtype).reshape(rows, -1)
+        for r in range(rows):
+            _check(got[r], x.reshape(rows, -1)[r], L, inverse, dtype)
+        for variant in (1, 3):
+            src[1:] = torch.from_numpy(x).cuda()
+            br.bitrev_dit_stages(s1, s1, stages=L, inverse=inverse, tile_bits=b, variant=variant)
+            got = to_host_bytes(s1).view(dtype).reshape(rows, -1)
+            for r in range(rows):
+                _check(got[r], x.reshape(rows, -1)[r], L, inverse, dtype)
+
+
 def test_dit_inplace_register_staged_full_size():
     x = workloads.complex64_normal(24, workloads.SEEDS["c2"])
     t = torch.from_numpy(x).cuda()
