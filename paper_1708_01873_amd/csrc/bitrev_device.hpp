@@ -806,9 +806,10 @@ __device__ __forceinline__ void tile_outofplace_elem(const typename Bytes<S>::T*
 // after the caller's barrier.  SERIAL: the partner's loads are issued only
 // once tile y has arrived and is scattered, rather than together with tile
 // y's.  Alternating rounds, kernel time, caches evicted: at b = 5 +1.6%
-// (complex64 2^24) and +0.6% (complex128 2^28); at b = 6 -1.3% (complex64
-// 2^26) to +1% (float32 2^30), so b = 6 keeps the joint loads.
-template <int S, int B, bool VEC, int NT, int H = kHintPlain, bool SERIAL = (B <= 5)>
+// (complex64 2^24) and +0.6% (complex128 2^28); float32 at b = 6 +0.3% to
+// +2.2% (2^24 to 2^30); complex64 at b = 6 -1.3% (2^26) to +0.6% (2^29),
+// so it keeps the joint loads.
+template <int S, int B, bool VEC, int NT, int H = kHintPlain, bool SERIAL = (B <= 5 || S == 4)>
 __device__ __forceinline__ void tile_pair_inplace(typename Bytes<S>::T* __restrict__ base, int m,
                                                   uint32_t y, typename Bytes<S>::T* lds) {
   if constexpr (tile_elementwise<S, B, VEC, NT>()) {
