@@ -375,9 +375,14 @@ def other_configs(torch, br, timer, reps: int) -> dict:
     # uint32, n = 2^10: launch-bound, reported in microseconds
     x = torch.from_numpy(workloads.uint32_uniform(10, workloads.SEEDS["c1"]).view("int32")).cuda()
     y = torch.empty_like(x)
+    # (per call with its dispatch, and the kernel alone from its own events)
     out["uint32_2p10"] = {
         "inplace_us": round(1e3 * med(timer.time(lambda: br.bitrev_inplace(x), reps)), 2),
-        "outofplace_us": round(1e3 * med(timer.time(lambda: br.bitrev_outofplace(x, y), reps)), 2)}
+        "outofplace_us": round(1e3 * med(timer.time(lambda: br.bitrev_outofplace(x, y), reps)), 2),
+        "inplace_kernel_us": round(1e3 * kernel_ms(
+            br, timer, lambda a, b: br.bitrev_inplace_timed(x, a, b), reps), 2),
+        "outofplace_kernel_us": round(1e3 * kernel_ms(
+            br, timer, lambda a, b: br.bitrev_outofplace_timed(x, y, a, b), reps), 2)}
     # the two 4 GiB arrays: beyond every cache, so their kernels are the
     # HBM-bound rooflines (kernel time from each launch's own events)
     for name, k, dt, seed in (("complex128_2p28", 28, torch.complex128, workloads.SEEDS["c3a"]),
