@@ -520,9 +520,8 @@ def main() -> int:
                     help="only run each main configuration a few times, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU form is a design "
-              "(see the sharding section of the design notes), so --gpus must be 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on one device and has no "
+              "multi-GPU form, so --gpus must be 1", file=sys.stderr)
         return 2
 
     import numpy as np
