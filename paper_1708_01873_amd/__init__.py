@@ -533,7 +533,8 @@ def bitrev_dit_stages(src, dst=None, stages: int = 1, *, inverse: bool = False, 
     """Bit reversal of each row (last dimension, complex64 or complex128)
     followed by the first `stages` radix-2 DIT FFT levels; ``dst is src``
     works in place.  Allocates ``dst`` when not given.  variant: 1 square
-    tiles, 2 / 3 rectangular tiles out of place (see the C header)."""
+    tiles, 2 / 3 rectangular tiles out of place, 3 in place the tile pair
+    held in registers (see the C header)."""
     import torch
     if src.dtype not in (torch.complex64, torch.complex128):
         raise TypeError("bitrev_dit_stages needs complex64 or complex128 data")
